@@ -1,0 +1,344 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms of the Hankel transform, special cases that reduce to textbook results,
+Parseval, an independent library routine, brute force on tiny inputs, or
+values the paper prints (tests/golden/).  Together they are chosen so that a
+dropped factor, a wrong sign or index, or a transposed operand anywhere in the
+oracle fails at least one of them.
+"""
+import json
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+from scipy.interpolate import CubicSpline
+from scipy.special import j1
+
+import workloads as W
+from oracle import adjoint as A
+from oracle import fft2d as F
+from oracle import hankel as H
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# Hankel matrix: closed forms (section 4.3, eq. ht)
+# ---------------------------------------------------------------------------
+def _chirp_gaussian_err(nr, w, sig=0.01):
+    """Gaussian under a quadratic (Fresnel) chirp: s = exp(-a r^2) with
+    a = 1/(2 sig^2) - j pi w has the 2D FT (pi/a) exp(-pi^2 rho^2 / a)."""
+    geo = H.geometry(200, 1e-3, nr, 4)          # r_max = 0.1 = 10 sigma
+    rho = np.linspace(0.0, 60.0, 121)
+    a = 1.0 / (2 * sig * sig) - 1j * math.pi * w
+    k = H.hankel_matrix(rho, geo) @ np.exp(-a * geo.r ** 2)
+    ref = (math.pi / a) * np.exp(-math.pi ** 2 * rho ** 2 / a)
+    return np.max(np.abs(k - ref)) / np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("w", [0.0, 100.0, 1000.0])
+def test_hankel_matrix_fresnel_gaussian_closed_form(w):
+    e1024 = _chirp_gaussian_err(1024, w)
+    e4096 = _chirp_gaussian_err(4096, w)
+    assert e4096 < 4e-7
+    # midpoint rule: second-order convergence in Nr
+    assert 12.0 < e1024 / e4096 < 20.0
+
+
+def test_hankel_w0_gaussian_closed_form():
+    """w = 0 reduces to the transform of the taper alone: 2 pi sig^2 exp(-2 pi^2 sig^2 rho^2)."""
+    sig = 0.01
+    geo = H.geometry(200, 1e-3, 4096, 4)
+    rho = np.linspace(0, 80, 161)
+    k = H.hankel_matrix(rho, geo) @ np.exp(-geo.r ** 2 / (2 * sig * sig))
+    ref = 2 * math.pi * sig * sig * np.exp(-2 * math.pi ** 2 * sig * sig * rho ** 2)
+    assert np.max(np.abs(k - ref)) / ref[0] < 4e-7
+
+
+@pytest.mark.parametrize("nr,tol", [(128, 1.5e-4), (8192, 3e-8)])
+def test_hankel_w0_disc_is_airy(nr, tol):
+    """Uniform disc of radius R: K(rho) = R J1(2 pi rho R) / rho (normalised by pi R^2)."""
+    geo = H.geometry(128, 7.8125e-4, nr, 4)
+    r_ = geo.r_max
+    rho = np.arange(1, 400) * geo.drho
+    k = H.hankel_matrix(rho, geo) @ np.ones(nr)
+    ref = r_ * j1(2 * math.pi * rho * r_) / rho
+    assert np.max(np.abs(k - ref)) / (math.pi * r_ * r_) < tol
+
+
+@pytest.mark.parametrize("w", [100.0, 1000.0, -700.0])
+def test_screen_and_hankel_disc_exact_phase_rho0(w):
+    """rho = 0 with the exact phase over the disc r <= R (uniform taper):
+    K(0) = 2 pi [F(1) - F(n_R)], F(n) = exp(c (n - 1)) (n / c - 1 / c^2),
+    c = -j 2 pi w, n_R = sqrt(1 - R^2).  Goes through oracle.hankel.screen,
+    so it pins the sign of the phase and the cancellation-free phi."""
+    geo = H.geometry(128, 7.8125e-4, 8192, 4)
+    c = -2j * math.pi * w
+
+    def fn(n):
+        return np.exp(c * (n - 1.0)) * (n / c - 1.0 / c ** 2)
+
+    ref = 2 * math.pi * (fn(1.0) - fn(math.sqrt(1.0 - geo.r_max ** 2)))
+    lines = H.radial_kernels(geo, np.ones(8192), np.array([w]), np.array([3]))
+    got = lines[0][0]
+    assert abs(got - ref) / abs(ref) < 2e-7
+    # the opposite sign of the phase would give the conjugate: far off
+    assert abs(np.conj(got) - ref) / abs(ref) > 1e-2
+
+
+def test_hankel_parseval():
+    """2 pi int |K|^2 rho d rho = 2 pi int tau^2 r dr, independent of w (|G| = 1)."""
+    geo = H.geometry(200, 1e-3, 4096, 4)
+    tau = np.exp(-geo.r ** 2 / (2 * 0.01 ** 2))
+    drho = 0.05
+    rho = np.arange(0, int(400 / drho)) * drho
+    m = H.hankel_matrix(rho, geo)
+    rhs = 2 * math.pi * np.sum(tau ** 2 * geo.r) * geo.dr
+    for w in (0.0, 100.0, 300.0):
+        k = m @ (tau * np.exp(2j * math.pi * w * geo.phi))
+        lhs = 2 * math.pi * np.sum(np.abs(k) ** 2 * rho) * drho
+        assert abs(lhs - rhs) / rhs < 2e-6
+
+
+def test_j0_against_mpmath():
+    """scipy's J0 (the oracle's) against mpmath's arbitrary-precision Bessel J0
+    over the argument range of the largest workload (2 pi rho_max r_max ~ 400)."""
+    from scipy.special import j0
+    xs = np.concatenate([np.linspace(0, 10, 41), np.linspace(10, 420, 83), [2.404825557695773]])
+    for x in xs:
+        # absolute error of a few ulp of the argument's phase (x * eps grows with x)
+        assert abs(j0(x) - float(mpmath.besselj(0, x))) < 1e-15 + 1e-17 * x
+
+
+def test_geometry_phi_cancellation_free():
+    geo = H.geometry(2048, W.ARCSEC * 3.5, 8192, 8)
+    with mpmath.workdps(60):
+        exact = np.array([float(1 - mpmath.sqrt(1 - mpmath.mpf(r) ** 2)) for r in geo.r[::511]])
+    assert np.max(np.abs(geo.phi[::511] - exact) / exact) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# invariants
+# ---------------------------------------------------------------------------
+def test_conjugate_symmetry_in_w():
+    """K(-w) = conj K(w) for a real taper (section 4.1)."""
+    wl = W.plain(extra_w=[-62.5, -937.5])
+    caches, _ = H.generate_workload(wl)
+    for p_pos, p_neg in ((0, 8), (7, 9)):
+        assert np.max(np.abs(caches[p_neg] - np.conj(caches[p_pos]))) <= 1e-15 * np.max(np.abs(caches[p_pos]))
+
+
+def test_linearity_in_taper():
+    wl = W.plain()
+    geo = H.geometry(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling)
+    rng = np.random.default_rng(W.SEED)
+    t1 = rng.normal(size=wl.n_radial)
+    t2 = rng.normal(size=wl.n_radial)
+    k1 = H.radial_kernels(geo, t1, wl.w, wl.support)
+    k2 = H.radial_kernels(geo, t2, wl.w, wl.support)
+    k12 = H.radial_kernels(geo, 0.3 * t1 - 1.7 * t2, wl.w, wl.support)
+    for a, b, c in zip(k1, k2, k12):
+        assert np.max(np.abs(c - (0.3 * a - 1.7 * b))) <= 1e-13 * np.max(np.abs(c))
+
+
+def test_supports_reach_only_existing_nodes():
+    for s in (1, 3, 7, 31, 127, 255):
+        for os_ in (1, 4, 8):
+            for q in (1, 2):
+                _, mask, t = H.sample_positions(s, os_, q)
+                n = int(H.n_rho([s], os_, q)[0])
+                h = (s - 1) // 2
+                # the farthest sample sits on node q os h; three nodes lie beyond it
+                assert t[mask].max() == q * os_ * h
+                assert n - 1 - q * os_ * h == 3
+
+
+# ---------------------------------------------------------------------------
+# interpolation (section 4.3.2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 3, 5, 28, 257])
+def test_spline_matches_scipy_cubicspline(n):
+    rng = np.random.default_rng(n)
+    y = rng.normal(size=n) + 1j * rng.normal(size=n)
+    m = H.spline_second_derivatives(y)
+    t = np.sort(rng.uniform(0, n - 1, 500))
+    x = np.arange(n, dtype=float)
+    ref = (CubicSpline(x, y.real, bc_type=((1, 0.0), (2, 0.0)))(t)
+           + 1j * CubicSpline(x, y.imag, bc_type=((1, 0.0), (2, 0.0)))(t))
+    got = H.spline_eval(y, m, t)
+    assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(y)))
+    # interpolation property at the nodes
+    assert np.max(np.abs(H.spline_eval(y, m, x) - y)) < 1e-13
+
+
+def test_spline_reproduces_admissible_cubic():
+    """A cubic with s'(0) = 0 and s''(n-1) = 0 is reproduced exactly."""
+    n = 40
+    c = 0.7
+    b = -3.0 * c * (n - 1)
+    f = lambda t: 2.0 + b * t ** 2 + c * t ** 3  # noqa: E731
+    x = np.arange(n, dtype=float)
+    m = H.spline_second_derivatives(f(x))
+    t = np.linspace(0, n - 1, 777)
+    assert np.max(np.abs(H.spline_eval(f(x), m, t) - f(t))) < 1e-9 * np.max(np.abs(f(t)))
+
+
+def test_linear_matches_numpy_interp():
+    rng = np.random.default_rng(3)
+    y = rng.normal(size=50)
+    t = rng.uniform(0, 49, 300)
+    assert np.max(np.abs(H.linear_eval(y, t) - np.interp(t, np.arange(50), y))) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# 2D-FFT twin (Algorithm 1)
+# ---------------------------------------------------------------------------
+def test_fft2d_matches_direct_dft():
+    fov = 0.1
+    n_ws = 16
+    os_ = 2
+    scr = F.workspace_screen(W.gaussian_taper(0.02), 300.0, n_ws, fov)
+    spec = F.padded_transform(scr, os_, fov)
+    xs, ys = np.meshgrid(np.arange(-6, 7), np.arange(-5, 6))
+    ref = F.direct_dft(scr, os_, fov, xs, ys)
+    c = spec.shape[0] // 2
+    got = spec[c + ys, c + xs]
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_fft2d_parseval():
+    fov, n_ws, os_ = 0.1, 64, 4
+    scr = F.workspace_screen(W.gaussian_taper(0.02), 500.0, n_ws, fov)
+    spec = F.padded_transform(scr, os_, fov)
+    dl = fov / n_ws
+    du = 1.0 / (os_ * n_ws * dl)
+    lhs = np.sum(np.abs(spec) ** 2) * du * du
+    rhs = np.sum(np.abs(scr) ** 2) * dl * dl
+    assert abs(lhs - rhs) / rhs < 1e-12
+
+
+def _hankel_exact_rho(geo, tau, w, support, os_):
+    """Hankel sum evaluated at each sample's exact radius (no spline)."""
+    d2, mask, _ = H.sample_positions(support, os_, 1)
+    uniq, inv = np.unique(d2[mask], return_inverse=True)
+    rho = geo.du * np.sqrt(uniq.astype(float)) / os_
+    vals = H.hankel_matrix(rho, geo) @ (np.asarray(tau, float) * np.exp(2j * math.pi * w * geo.phi))
+    out = np.zeros(mask.shape, complex)
+    out[mask] = vals[inv]
+    return out, mask
+
+
+def test_hankel_vs_2d_in_circle_plain():
+    """Section 4.4: the Hankel route equals the 2D FFT route inside the circular
+    region.  Plain workload (Gaussian sigma 0.02 cut at r_max = 0.05): the
+    remaining difference is the Cartesian staircase of the disc edge."""
+    wl = W.plain()
+    caches, _ = H.generate_workload(wl)
+    ffts = F.generate(wl.taper_fn, wl.w, wl.support, wl.oversampling, 128, wl.image_size * wl.cellsize)
+    for c_h, c_f in zip(caches, ffts):
+        assert np.max(np.abs(c_h - c_f)) / np.max(np.abs(c_f)) < 1e-3
+
+
+def test_hankel_vs_2d_in_circle_smooth_edge():
+    """With a taper that vanishes smoothly at r_max the two routes agree to the
+    quadrature error (exact-radius Hankel at Nr = 4096 vs 2D DFT)."""
+    r_max = 0.05
+    base = W.gaussian_taper(0.02)
+    fn = lambda r: base(r) * np.clip(1 - (np.asarray(r) / r_max) ** 2, 0, None) ** 2  # noqa: E731
+    geo = H.geometry(128, 7.8125e-4, 4096, 4)
+    tau = fn(geo.r)
+    for w in (62.5, 562.5, 937.5):
+        ref, mask = _hankel_exact_rho(geo, tau, w, 31, 4)
+        got = F.generate(fn, [w], [31], 4, 128, 0.1)[0]
+        assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-6
+
+
+def test_resample_layout_against_exact_radius():
+    """The spline cache at refinement q = 4 matches the exact-radius Hankel sum:
+    pins the sample offsets X, Y, the circular mask and the radial scale."""
+    geo = H.geometry(128, 7.8125e-4, 128, 4, radial_refine=4)
+    wl = W.plain()
+    caches, _ = H.generate(128, 7.8125e-4, 128, 4, wl.taper, wl.w, wl.support, radial_refine=4)
+    for p in (0, 5, 7):
+        ref, _ = _hankel_exact_rho(geo, wl.taper, wl.w[p], 31, 4)
+        assert np.max(np.abs(caches[p] - ref)) / np.max(np.abs(ref)) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# gradient (adjoint)
+# ---------------------------------------------------------------------------
+def _small_grad_case():
+    wl = W.random_small(11, n_planes=4, n_radial=48, os_=2, max_support=15)
+    wl.support[:] = np.array([15, 11, 13, 9], dtype=np.int32)
+    return wl
+
+
+def _loss(wl, tau, w):
+    caches, _ = H.generate(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, tau, w,
+                           wl.support, wl.radial_refine, wl.interp)
+    return A.energy_outside_loss(caches, wl.support, wl.oversampling, inner_half=2)
+
+
+@pytest.mark.parametrize("interp", ["cubic", "linear"])
+def test_adjoint_matches_central_fd(interp):
+    wl = _small_grad_case()
+    wl.interp = interp
+    tau = wl.taper.astype(np.float64)
+    w = wl.w.copy()
+    loss, g = _loss(wl, tau, w)
+    g_tau, g_w = A.grad(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, tau, w,
+                        wl.support, g, wl.radial_refine, interp)
+    h = 1e-4
+    fd_tau = np.zeros_like(tau)
+    for i in range(len(tau)):
+        tp, tm = tau.copy(), tau.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd_tau[i] = (_loss(wl, tp, w)[0] - _loss(wl, tm, w)[0]) / (2 * h)
+    fd_w = np.zeros_like(w)
+    for p in range(len(w)):
+        wp, wm = w.copy(), w.copy()
+        wp[p] += h
+        wm[p] -= h
+        fd_w[p] = (_loss(wl, tau, wp)[0] - _loss(wl, tau, wm)[0]) / (2 * h)
+    assert np.max(np.abs(g_tau - fd_tau)) / np.max(np.abs(fd_tau)) < 1e-6
+    assert np.max(np.abs(g_w - fd_w)) / np.max(np.abs(fd_w)) < 1e-6
+
+
+@pytest.mark.parametrize("interp", ["cubic", "linear"])
+def test_resample_adjoint_dot_product(interp):
+    rng = np.random.default_rng(5)
+    s, os_, q = 13, 3, 2
+    n = int(H.n_rho([s], os_, q)[0])
+    y = rng.normal(size=n) + 1j * rng.normal(size=n)
+    g = rng.normal(size=(os_, os_, s, s)) + 1j * rng.normal(size=(os_, os_, s, s))
+    ry = H.resample(y, s, os_, q, interp)
+    lhs = np.real(np.vdot(g, ry))
+    rhs = np.real(np.vdot(A.resample_adjoint(g, n, s, os_, q, interp), y))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ---------------------------------------------------------------------------
+# sizing statements the paper prints (tests/golden/paper_sizing.json)
+# ---------------------------------------------------------------------------
+def test_paper_sizing_statements():
+    with open(os.path.join(GOLDEN, "paper_sizing.json")) as f:
+        g = json.load(f)
+    kc = g["kernel_cache_counts"]
+    assert kc["oversampling"] ** 2 == kc["kernels_per_plane"]
+    assert kc["oversampling"] ** 2 * kc["n_planes"] == kc["kernels_total"]
+    sw = g["support_to_width"]
+    assert 2 * sw["half_support"] + 1 == sw["full_width"]
+    # the oracle's layout gives a full width S block per sub-kernel
+    offs = H.offsets([sw["full_width"]], kc["oversampling"])
+    assert offs[1] == kc["kernels_per_plane"] * sw["full_width"] ** 2
+    wu = g["workspace_undersampling"]
+    for hs, ws, fs in zip(wu["half_support"], wu["workspace"], wu["fft_size"]):
+        assert F.next_pow2(2 * hs + 1) == ws
+        assert wu["oversampling"] * ws == fs
+    pf = g["padded_full_image"]
+    assert pf["image_size"] * pf["oversampling"] == pf["padded"]
+    assert round(pf["padded"] ** 2 * 16 / 1e9) == pf["gigabytes"]
