@@ -1,0 +1,173 @@
+/*
+ * wkern.h -- w-projection convolution-kernel generation on AMD Instinct MI355X
+ * (gfx950), C ABI.
+ *
+ * Method: Lucas, Skipper & Scaife (2019), "Fast W-Projection for Wide-field
+ * Imaging", section 4 and Algorithm 2.  For every w-plane the library
+ *   1. evaluates the radially symmetric image-domain convolution kernel
+ *      s(r) = tau(r) * G(r, w) on radial nodes, with G the w-projection
+ *      screen of section 2.5 (equation wproj_G):
+ *          G = exp(-j 2 pi w (sqrt(1 - r^2) - 1)) = exp(+j 2 pi w phi(r)),
+ *          phi(r) = r^2 / (1 + sqrt(1 - r^2)), formed in FP64;
+ *   2. takes it to the uv plane with the order-0 Hankel transform (section
+ *      4.3, equation ht) applied as the product of a discrete HT matrix,
+ *      built once per plan, with the sampled screen:
+ *          K_p(rho_k) = sum_i M[k, i] s_p(r_i),
+ *          M[k, i]    = 2 pi J0(2 pi rho_k r_i) r_i dr,
+ *          r_i = (i + 1/2) dr, dr = r_max / Nr, r_max = image_size*cellsize/2,
+ *          rho_k = k du / (q os), du = 1 / (image_size * cellsize),
+ *          k = 0 .. q os h_p + 3;
+ *   3. interpolates the radial line with a cubic spline (s'(0) = 0, natural
+ *      at the last node) or linearly (section 4.3.2) onto the oversampled
+ *      kernel cache over the circular support (section 4.4, Algorithm 2).
+ *
+ * Output layout (kernel cache).  Plane p (caller order) of odd full width
+ * S_p (half-width h_p = (S_p - 1) / 2) occupies os*os*S_p*S_p complex64
+ * values starting at offsets[p] (prefix sum, see wkern_layout):
+ *     out[offsets[p] + ((fv*os + fu)*S_p + b)*S_p + a],  fv, fu in [0, os),
+ *     b, a in [0, S_p), holds K_p at uv offset ((a - h) - fu/os,
+ *     (b - h) - fv/os) cells, i.e. X = os (a - h) - fu, Y = os (b - h) - fv,
+ *     radius rho = du sqrt(X^2 + Y^2) / os, when X^2 + Y^2 <= (os h)^2, and
+ *     exactly 0 outside that disc.
+ * complex64 = two floats (re, im), the layout of C99 float _Complex and of
+ * torch.complex64.
+ *
+ * Conventions.
+ * - Every call returns a wkern_status.  No C++ exception crosses the ABI.
+ *   On any error a detail string is available from wkern_last_error() (per
+ *   thread, valid until the next call on that thread).
+ * - Host-side validation completes before anything is enqueued: on an error
+ *   status from a generating call nothing has been written.
+ * - Device pointers are HIP device pointers on the plan's device.  The
+ *   caller owns every buffer it passes; the plan owns its own tables and
+ *   scratch.  Buffers must not alias each other.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls on
+ *   one plan must not overlap in time: a plan serves one stream at a time.
+ * - Generating calls are asynchronous with respect to the host.
+ */
+#ifndef WKERN_H
+#define WKERN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WKERN_ABI_VERSION 1
+
+typedef enum {
+  WKERN_OK = 0,
+  WKERN_ERR_INVALID_ARG = 1,   /* argument fails validation; nothing enqueued */
+  WKERN_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
+  WKERN_ERR_DEVICE = 3,        /* no usable device or a HIP runtime error */
+  WKERN_ERR_UNSUPPORTED = 4,   /* valid request this build does not implement */
+  WKERN_ERR_ABI_MISMATCH = 5   /* desc->abi_version != WKERN_ABI_VERSION */
+} wkern_status;
+
+/* Arithmetic of the Hankel contraction (step 2).  The phase is always formed
+ * in FP64.  FP32: M and s rounded to FP32, FP32 matrix-core products.
+ * BF16X6: M and s each split into three BF16 terms (x ~ x0 + x1 + x2) and
+ * combined with six products (02, 11, 20, 01, 10, 00).  Both accumulate in
+ * FP32 over K-chunks of at most 256 radial nodes and combine chunks in FP64. */
+typedef enum { WKERN_PREC_FP32 = 0, WKERN_PREC_BF16X6 = 1 } wkern_precision;
+
+/* Interpolation of the radial line (section 4.3.2). */
+typedef enum { WKERN_INTERP_LINEAR = 0, WKERN_INTERP_CUBIC = 1 } wkern_interp;
+
+typedef struct wkern_plan_s* wkern_plan_t; /* opaque, owned by the library */
+
+/* Problem description; arguments follow the paper's statement of the
+ * problem: per-plane w (Algorithm 2), image and cell size (section 5,
+ * imager settings), IAA taper (Algorithm 2), maximum support (section 4.2
+ * and section 5 settings), oversampling (section 3.1), interpolation type
+ * (section 4.3.2). */
+typedef struct {
+  int32_t abi_version;     /* must be WKERN_ABI_VERSION */
+  int32_t image_size;      /* N pixels; FOV = N * cellsize; r_max = FOV / 2 */
+  double cellsize;         /* radians, direction-cosine increment; r_max < 1 */
+  int32_t n_radial;        /* Nr >= 1: midpoint nodes over [0, r_max] */
+  int32_t oversampling;    /* os in [1, 64] */
+  int32_t radial_refine;   /* q in [1, 16]; 1 = spacing du/os (section 4.4) */
+  int32_t n_planes;        /* P >= 1: w-planes x channels */
+  const int32_t* support;  /* host [P]: odd full widths, 1 <= S_p <= max_support */
+  int32_t max_support;     /* odd, >= 1; os * max_support <= 4096 */
+  wkern_precision precision;
+  wkern_interp interp;
+  int32_t device;          /* HIP device ordinal */
+} wkern_desc;
+
+/* Version of the ABI this library was built with (== WKERN_ABI_VERSION). */
+int32_t wkern_abi_version(void);
+
+/* Layout of the kernel cache for a description, on the host only (no device
+ * is touched).  offsets: host [P + 1], complex elements, offsets[P] = total.
+ * nrho: host [P] radial nodes per plane (q os h_p + 4), may be NULL.
+ * Errors: WKERN_ERR_INVALID_ARG / WKERN_ERR_ABI_MISMATCH as for wkern_plan. */
+wkern_status wkern_layout_desc(const wkern_desc* d, int64_t* offsets, int32_t* nrho);
+
+/* Build a plan: validates d, computes the geometry in FP64, the discrete HT
+ * matrix M (section 4.3: computed once) on the device with FP64 J0, the
+ * plane order and tile schedule, and allocates all scratch.  Synchronous.
+ * The description (including `support`) is copied; the caller keeps
+ * ownership of d.  On error *out is set to NULL and nothing leaks.
+ * Errors: INVALID_ARG (a field out of range, a NULL pointer, an even or too
+ * large support, r_max >= 1), ABI_MISMATCH, DEVICE (no such device / HIP
+ * failure), OUT_OF_MEMORY. */
+wkern_status wkern_plan(const wkern_desc* d, wkern_plan_t* out);
+
+/* Same layout as wkern_layout_desc for the plan's description. */
+wkern_status wkern_layout(wkern_plan_t plan, int64_t* offsets, int32_t* nrho);
+
+/* Generate every plane's kernel cache (steps 1-3).
+ * taper: device float [Nr], tau at r_i (caller owned, read only).
+ * w:     device double [P], w of each plane in wavelengths (read only).
+ * out:   device complex64 [offsets[P]] (written completely, zeros included).
+ * Asynchronous on `stream`.  Errors: INVALID_ARG (NULL plan or pointer),
+ * DEVICE (launch failure). */
+wkern_status wkern_generate(wkern_plan_t plan, const float* taper, const double* w,
+                            void* out, void* stream);
+
+/* Steps 1-2 only: the radial lines, for inspection and tests.
+ * lines: device complex128 (two doubles) [sum_p nrho[p]], plane p's line at
+ * the prefix sum of nrho over planes before p (caller order); line p holds
+ * K_p(rho_k), k = 0 .. nrho[p] - 1.  Asynchronous on `stream`. */
+wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const double* w,
+                                   void* lines, void* stream);
+
+/* Gradient of a real loss L of the kernel cache (reverse of steps 1-3; the
+ * paper has no gradient, this is the chain rule through the steps above).
+ * grad_out:   device complex64 [offsets[P]], dL/dRe + j dL/dIm of each value.
+ * grad_taper: device float [Nr] (written), dL/dtau_i.
+ * grad_w:     device double [P] (written), dL/dw_p.
+ * Asynchronous on `stream`.  Errors: INVALID_ARG, DEVICE. */
+wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
+                        const void* grad_out, float* grad_taper, double* grad_w,
+                        void* stream);
+
+/* Stage timing of wkern_generate with HIP events recorded on the call's own
+ * stream around each stage (0 screen, 1 contraction, 2 spline, 3 resample);
+ * recording adds no synchronisation.  enable != 0 clears and starts
+ * accumulation, enable == 0 stops it.  Errors: INVALID_ARG, DEVICE. */
+wkern_status wkern_set_profiling(wkern_plan_t plan, int32_t enable);
+
+/* Waits for the recorded events and returns the summed milliseconds of each
+ * stage (ms: host double [4]) and the number of profiled generate calls
+ * (calls: host, may be NULL).  Errors: INVALID_ARG, DEVICE. */
+wkern_status wkern_stage_times(wkern_plan_t plan, double* ms, int32_t* calls);
+
+/* Release the plan and everything it owns.  Synchronises the plan's device
+ * first.  NULL is accepted and ignored. */
+wkern_status wkern_destroy(wkern_plan_t plan);
+
+/* Static description of a status code. */
+const char* wkern_strerror(wkern_status s);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char* wkern_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WKERN_H */

@@ -1,0 +1,101 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wkern {
+
+// Radial K-chunk accumulated in FP32 inside the matrix cores before it is
+// added to an FP64 running sum.
+constexpr int kSubChunk = 128;
+// Granularity of the padded radial-node count (a multiple of kSubChunk).
+constexpr int kNrAlign = 256;
+// Rows of M are padded to this multiple (largest row tile).
+constexpr int kRowAlign = 128;
+// Columns (plane x {re, im}) are padded to this multiple (largest column tile).
+constexpr int kColAlign = 128;
+// Largest radial line a plane may have (sets the spline's LDS footprint).
+constexpr int kMaxRho = 2048;
+// Warm-up length of the truncated spline recurrences; the neglected start
+// value is damped by (2 - sqrt 3)^32 ~ 5e-19.
+constexpr int kSplineWarm = 32;
+
+// Exact division of n < 2^24 by d < 2^16 with one 64-bit multiply:
+// q = (n * m) >> 40, m = floor(2^40 / d) + 1.
+struct FastDiv {
+  uint64_t m;
+  uint32_t d;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  f.m = ((uint64_t)1 << 40) / d + 1;
+  return f;
+}
+
+// Per-plane table used by the resampler (caller order).
+struct PlaneInfo {
+  int64_t out_off;    // complex64 offset of the plane's cache
+  int32_t line_off;   // offset of its radial line / spline intervals (sorted order)
+  int32_t nrho;       // radial nodes
+  int32_t S;          // full width
+  int32_t h;          // half width
+  int32_t lim;        // (os h)^2
+  int32_t pad;
+  FastDiv divS;
+};
+
+// One block of output elements [e0, e1) of plane p (plane-local indices).
+struct ResampleUnit {
+  int32_t p;
+  int32_t e0;
+  int32_t e1;
+  int32_t pad;
+};
+
+// One contraction tile: rows [row0, row0 + rows), sorted columns
+// [col0, col0 + cols), radial nodes [k0, k1).
+struct Tile {
+  int32_t row0;
+  int32_t col0;
+  int32_t k0;
+  int32_t kc;   // index of the K-chunk (partial-sum slot)
+};
+
+struct DevPlan {
+  // geometry
+  int P, Nr, NrPad, os, q, nrhoMax, rowsPad, colsPad, lineTotal, nkc, kchunk;
+  int interp;     // 0 linear, 1 cubic
+  int precision;  // 0 fp32, 1 bf16x6
+  double dr, drho;
+  // device tables
+  double* phi;            // [NrPad]
+  float* M32;             // [rowsPad][NrPad]
+  uint16_t* Msplit;       // [rowsPad][NrPad/8][3][8]
+  int32_t* perm;          // [P] sorted j -> caller p
+  int32_t* nrhoSorted;    // [P]
+  int32_t* lineOffSorted; // [P + 1]
+  double* cprime;         // [nrhoMax] Thomas coefficients
+  PlaneInfo* planes;      // [P] caller order
+  Tile* tiles;
+  int nTiles;
+  ResampleUnit* units;
+  int nUnits;
+  // scratch
+  float* B32;             // [colsPad][NrPad]
+  uint16_t* Bsplit;       // [colsPad][NrPad/8][3][8]
+  double* part;           // [nkc][lineTotal][2]
+  float4* coef;           // [lineTotal][2]
+};
+
+hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s);
+hipError_t launch_screen(const DevPlan& p, const float* taper, const double* w, hipStream_t s);
+hipError_t launch_contract(const DevPlan& p, hipStream_t s);
+hipError_t launch_spline(const DevPlan& p, hipStream_t s);
+hipError_t launch_resample(const DevPlan& p, void* out, hipStream_t s);
+hipError_t launch_lines_out(const DevPlan& p, const int32_t* lineOffCaller, void* lines,
+                            hipStream_t s);
+
+}  // namespace wkern

@@ -1,0 +1,547 @@
+// HIP kernels for w-projection kernel generation on gfx950 (MI355X).
+//
+// Pipeline of one generate call (Lucas, Skipper & Scaife 2019, Algorithm 2):
+//   k_screen_*     image-domain kernel s[i, p] = tau_i exp(+j 2 pi w_p phi_i)
+//                  (section 2.5, eq. wproj_G, times the IAA-kernel), phase
+//                  reduced in FP64;
+//   k_contract_*   order-0 Hankel transform as K = M s on the matrix cores
+//                  (section 4.3, eq. ht; the HT matrix M is built once per
+//                  plan by k_hankel_matrix);
+//   k_spline       spline coefficients of each radial line (section 4.3.2);
+//   k_resample     oversampled 2D kernels over the circular support
+//                  (section 4.4, Algorithm 2).
+#include "wkern_internal.h"
+
+namespace wkern {
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f(uint16_t h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ uint32_t fastdiv(uint32_t n, FastDiv f) {
+  return (uint32_t)(((uint64_t)n * f.m) >> 40);
+}
+
+// --------------------------------------------------------------------------
+// Discrete HT matrix (section 4.3): M[k, i] = 2 pi J0(2 pi rho_k r_i) r_i dr,
+// midpoint nodes r_i = (i + 1/2) dr, rho_k = k drho.  FP64 with the device
+// j0; stored as FP32 and as three BF16 terms split from the FP64 value,
+// grouped by 8 radial nodes: Msplit[k][i/8][term][i%8].
+// --------------------------------------------------------------------------
+__global__ void k_hankel_matrix(int rowsPad, int NrPad, int Nr, int nrhoMax, double dr,
+                                double drho, float* __restrict__ M32,
+                                uint16_t* __restrict__ Msplit) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= NrPad || k >= rowsPad) return;
+  double m = 0.0;
+  if (i < Nr && k < nrhoMax) {
+    const double r = (i + 0.5) * dr;
+    const double rho = k * drho;
+    m = kTwoPi * j0(kTwoPi * rho * r) * r * dr;
+  }
+  M32[(size_t)k * NrPad + i] = (float)m;
+  const uint16_t t0 = bf16_rne((float)m);
+  double rem = m - (double)bf16_to_f(t0);
+  const uint16_t t1 = bf16_rne((float)rem);
+  rem -= (double)bf16_to_f(t1);
+  const uint16_t t2 = bf16_rne((float)rem);
+  const size_t base = ((size_t)k * (NrPad / 8) + (i >> 3)) * 24 + (i & 7);
+  Msplit[base] = t0;
+  Msplit[base + 8] = t1;
+  Msplit[base + 16] = t2;
+}
+
+// --------------------------------------------------------------------------
+// Screen (section 2.5 eq. wproj_G times the IAA-kernel, Algorithm 2):
+// s = tau exp(+j 2 pi w phi).  t = w phi is reduced modulo 1 in FP64; the
+// FP32 sincospi of the reduced phase is corrected to first order with the
+// FP64 remainder, so the value is accurate well beyond FP32 rounding of t.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float2 screen_value(double wv, double ph, float tau) {
+  double t = wv * ph;
+  t -= rint(t);
+  const float th = (float)t;
+  const float dl = (float)((t - (double)th) * kTwoPi);
+  float sn, cs;
+  sincospif(2.0f * th, &sn, &cs);
+  const float c2 = cs - dl * sn;
+  const float s2 = sn + dl * cs;
+  return make_float2(tau * c2, tau * s2);
+}
+
+// FP32 screen: B32[2j + c][i], sorted plane j, c = 0 (re) / 1 (im).
+__global__ void k_screen_f32(int P, int Nr, int NrPad, const int32_t* __restrict__ perm,
+                             const double* __restrict__ phi, const float* __restrict__ taper,
+                             const double* __restrict__ w, float* __restrict__ B32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NrPad) return;
+  for (int j = blockIdx.y; j < P; j += gridDim.y) {
+    const double wv = w[perm[j]];
+    float2 v = make_float2(0.f, 0.f);
+    if (i < Nr) v = screen_value(wv, phi[i], taper[i]);
+    B32[(size_t)(2 * j) * NrPad + i] = v.x;
+    B32[(size_t)(2 * j + 1) * NrPad + i] = v.y;
+  }
+}
+
+// Split-BF16 screen: Bsplit[col][i/8][term][i%8]; one thread per 8 nodes.
+__global__ void k_screen_bf16(int P, int Nr, int NrPad, const int32_t* __restrict__ perm,
+                              const double* __restrict__ phi, const float* __restrict__ taper,
+                              const double* __restrict__ w, uint16_t* __restrict__ Bsplit) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;  // group of 8 nodes
+  const int ng = NrPad / 8;
+  if (g >= ng) return;
+  for (int j = blockIdx.y; j < P; j += gridDim.y) {
+    const double wv = w[perm[j]];
+    uint16_t re[3][8], im[3][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int i = g * 8 + e;
+      float2 v = make_float2(0.f, 0.f);
+      if (i < Nr) v = screen_value(wv, phi[i], taper[i]);
+      float x = v.x;
+      uint16_t a0 = bf16_rne(x);
+      x -= bf16_to_f(a0);
+      uint16_t a1 = bf16_rne(x);
+      x -= bf16_to_f(a1);
+      re[0][e] = a0;
+      re[1][e] = a1;
+      re[2][e] = bf16_rne(x);
+      float y = v.y;
+      uint16_t b0 = bf16_rne(y);
+      y -= bf16_to_f(b0);
+      uint16_t b1 = bf16_rne(y);
+      y -= bf16_to_f(b1);
+      im[0][e] = b0;
+      im[1][e] = b1;
+      im[2][e] = bf16_rne(y);
+    }
+    uint4* dre = (uint4*)(Bsplit + ((size_t)(2 * j) * ng + g) * 24);
+    uint4* dim = (uint4*)(Bsplit + ((size_t)(2 * j + 1) * ng + g) * 24);
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      uint4 a, b;
+      a.x = re[t][0] | ((uint32_t)re[t][1] << 16);
+      a.y = re[t][2] | ((uint32_t)re[t][3] << 16);
+      a.z = re[t][4] | ((uint32_t)re[t][5] << 16);
+      a.w = re[t][6] | ((uint32_t)re[t][7] << 16);
+      b.x = im[t][0] | ((uint32_t)im[t][1] << 16);
+      b.y = im[t][2] | ((uint32_t)im[t][3] << 16);
+      b.z = im[t][4] | ((uint32_t)im[t][5] << 16);
+      b.w = im[t][6] | ((uint32_t)im[t][7] << 16);
+      dre[t] = a;
+      dim[t] = b;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Hankel contraction K[k, c] = sum_i M[k, i] B[c, i] over one K-chunk of a
+// tile.  One wave per tile of 32 rows x 32*CB columns; 32x32 MFMA output
+// blocks (lane l holds column l%32, rows 8*(r/4) + 4*(l/32) + r%4 of its
+// 16 accumulators).  The radial index is permuted identically for A and B
+// inside each K-step, which leaves the sum unchanged.  Every kSubChunk nodes
+// the FP32 matrix-core sums are added to FP64 running sums.
+// --------------------------------------------------------------------------
+template <int CB>
+__device__ __forceinline__ void store_tile(const Tile& t, const double (*accd)[16], int P,
+                                           int lineTotal, const int32_t* __restrict__ nrhoSorted,
+                                           const int32_t* __restrict__ lineOffSorted,
+                                           double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int col = t.col0 + 32 * cb + rr;
+    const int j = col >> 1;
+    const int comp = col & 1;
+    if (j >= P) continue;
+    const int nr = nrhoSorted[j];
+    double* dst = part + ((size_t)t.kc * lineTotal + lineOffSorted[j]) * 2 + comp;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = t.row0 + 8 * (r >> 2) + 4 * hb + (r & 3);
+      if (row < nr) dst[(size_t)row * 2] = accd[cb][r];
+    }
+  }
+}
+
+template <int CB>
+__global__ __launch_bounds__(64) void k_contract_f32(
+    const Tile* __restrict__ tiles, int NrPad, int kchunk, int P, int lineTotal,
+    const float* __restrict__ M32, const float* __restrict__ B32,
+    const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
+    double* __restrict__ part) {
+  const Tile t = tiles[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+  const float* arow = M32 + (size_t)(t.row0 + rr) * NrPad + 4 * hb;
+  const float* bcol[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) bcol[cb] = B32 + (size_t)(t.col0 + 32 * cb + rr) * NrPad + 4 * hb;
+  double accd[CB][16];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accd[cb][r] = 0.0;
+
+  for (int ks = t.k0; ks < t.k0 + kchunk; ks += kSubChunk) {
+    f32x16 acc[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[cb][r] = 0.f;
+#pragma unroll 4
+    for (int k0 = ks; k0 < ks + kSubChunk; k0 += 8) {
+      const float4 a4 = *(const float4*)(arow + k0);
+      float4 b4[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) b4[cb] = *(const float4*)(bcol[cb] + k0);
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, b4[cb].x, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, b4[cb].y, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, b4[cb].z, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, b4[cb].w, acc[cb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) accd[cb][r] += (double)acc[cb][r];
+  }
+  store_tile<CB>(t, accd, P, lineTotal, nrhoSorted, lineOffSorted, part);
+}
+
+// Split-BF16: A = A0 + A1 + A2, B = B0 + B1 + B2; six products per K-step,
+// the five small ones (02, 11, 20, 01, 10) accumulated apart from 00 so that
+// their rounding stays at their own (2^-8 smaller) scale.
+template <int CB>
+__global__ __launch_bounds__(64) void k_contract_bf16x6(
+    const Tile* __restrict__ tiles, int NrPad, int kchunk, int P, int lineTotal,
+    const uint16_t* __restrict__ Msplit, const uint16_t* __restrict__ Bsplit,
+    const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
+    double* __restrict__ part) {
+  const Tile t = tiles[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+  const int ng = NrPad / 8;
+  const uint4* arow = (const uint4*)(Msplit + ((size_t)(t.row0 + rr) * ng + hb) * 24);
+  const uint4* bcol[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+    bcol[cb] = (const uint4*)(Bsplit + ((size_t)(t.col0 + 32 * cb + rr) * ng + hb) * 24);
+  double accd[CB][16];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accd[cb][r] = 0.0;
+
+  for (int ks = t.k0; ks < t.k0 + kchunk; ks += kSubChunk) {
+    f32x16 hi[CB], lo[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        hi[cb][r] = 0.f;
+        lo[cb][r] = 0.f;
+      }
+#pragma unroll 2
+    for (int k0 = ks; k0 < ks + kSubChunk; k0 += 16) {
+      // group index of this lane's 8 nodes: k0/8 + hb (hb folded into the base)
+      const uint4* ap = arow + (size_t)(k0 >> 3) * 3;
+      const bf16x8 a0 = as_bf16x8(ap[0]);
+      const bf16x8 a1 = as_bf16x8(ap[1]);
+      const bf16x8 a2 = as_bf16x8(ap[2]);
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const uint4* bp = bcol[cb] + (size_t)(k0 >> 3) * 3;
+        const bf16x8 b0 = as_bf16x8(bp[0]);
+        const bf16x8 b1 = as_bf16x8(bp[1]);
+        const bf16x8 b2 = as_bf16x8(bp[2]);
+        lo[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b2, lo[cb], 0, 0, 0);
+        lo[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, lo[cb], 0, 0, 0);
+        lo[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b0, lo[cb], 0, 0, 0);
+        lo[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, lo[cb], 0, 0, 0);
+        lo[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, lo[cb], 0, 0, 0);
+        hi[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, hi[cb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) accd[cb][r] += (double)hi[cb][r] + (double)lo[cb][r];
+  }
+  store_tile<CB>(t, accd, P, lineTotal, nrhoSorted, lineOffSorted, part);
+}
+
+// --------------------------------------------------------------------------
+// Spline coefficients (section 4.3.2).  One wave per sorted plane.  The
+// second derivatives m of the interpolating cubic spline with s'(0) = 0 and
+// s''(n-1) = 0 solve T m = d with rows
+//   2 m_0 + m_1 = 6 (y_1 - y_0),
+//   m_{k-1} + 4 m_k + m_{k+1} = 6 (y_{k-1} - 2 y_k + y_{k+1}),  m_{n-1} = 0.
+// Thomas elimination: d'_0 = d_0 / 2, d'_k = (d_k - d'_{k-1}) c'_k with the
+// data-independent c'_0 = 1/2, c'_k = 1 / (4 - c'_{k-1}) (table from the
+// plan), then m_k = d'_k - c'_k m_{k+1}.  Both recurrences damp an error in
+// their start value by c'_k ~ 0.268 per step, so each lane runs them over
+// its own segment of nodes from kSplineWarm nodes outside it with a zero
+// start value (exact at the ends of the line, where the true start values
+// are known) and no lane waits for another.  The partial sums of the
+// contraction's K-chunks are combined here in FP64.
+// Output per interval k: power-form coefficients c0..c3 of re and im,
+//   s(k + u) = c0 + u (c1 + u (c2 + u c3)),  u in [0, 1).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_spline(int nkc, int lineTotal, int interp,
+                                               const int32_t* __restrict__ nrhoSorted,
+                                               const int32_t* __restrict__ lineOffSorted,
+                                               const double* __restrict__ cprime,
+                                               const double* __restrict__ part,
+                                               float4* __restrict__ coef) {
+  extern __shared__ double2 smem[];
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int n = nrhoSorted[j];
+  const int off = lineOffSorted[j];
+  double2* y = smem;           // [n] radial line
+  double2* dp = smem + n;      // [n] eliminated right-hand side d'
+  double2* m = smem + 2 * n;   // [n] second derivatives
+
+  for (int k = lane; k < n; k += 64) {
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < nkc; ++c) {
+      const double2 v = ((const double2*)part)[(size_t)c * lineTotal + off + k];
+      re += v.x;
+      im += v.y;
+    }
+    y[k] = make_double2(re, im);
+  }
+  __syncthreads();
+
+  const int L = (n + 63) / 64;
+  const int s = min(lane * L, n);
+  const int e = min(s + L, n);
+
+  if (interp == 1) {
+    // forward elimination over rows 0 .. n-2 (row n-1 gives d' = 0)
+    {
+      const int start = max(0, s - kSplineWarm);
+      double2 prev = make_double2(0.0, 0.0);
+      for (int k = start; k < e; ++k) {
+        double2 v;
+        if (k == n - 1) {
+          v = make_double2(0.0, 0.0);
+        } else if (k == 0) {
+          v.x = 6.0 * (y[1].x - y[0].x) * cprime[0];
+          v.y = 6.0 * (y[1].y - y[0].y) * cprime[0];
+        } else {
+          const double dx = 6.0 * (y[k - 1].x - 2.0 * y[k].x + y[k + 1].x);
+          const double dy = 6.0 * (y[k - 1].y - 2.0 * y[k].y + y[k + 1].y);
+          v.x = (dx - prev.x) * cprime[k];
+          v.y = (dy - prev.y) * cprime[k];
+        }
+        prev = v;
+        if (k >= s) dp[k] = v;
+      }
+    }
+    __syncthreads();
+    // back substitution: m_{n-1} = 0, m_k = d'_k - c'_k m_{k+1}
+    {
+      const int top = min(n - 1, e - 1 + kSplineWarm);
+      double2 next = make_double2(0.0, 0.0);  // m_{top + 1}; exact when top == n-1
+      for (int k = top; k >= s; --k) {
+        double2 v;
+        if (k == n - 1) {
+          v = make_double2(0.0, 0.0);
+        } else {
+          v.x = dp[k].x - cprime[k] * next.x;
+          v.y = dp[k].y - cprime[k] * next.y;
+        }
+        next = v;
+        if (k < e) m[k] = v;
+      }
+    }
+    __syncthreads();
+  }
+
+  for (int k = s; k < e; ++k) {
+    float4 cr, ci;
+    if (k <= n - 2) {
+      const double2 y0 = y[k], y1 = y[k + 1];
+      if (interp == 1) {
+        const double2 m0 = m[k], m1 = m[k + 1];
+        cr = make_float4((float)y0.x, (float)(y1.x - y0.x - m0.x / 3.0 - m1.x / 6.0),
+                         (float)(0.5 * m0.x), (float)((m1.x - m0.x) / 6.0));
+        ci = make_float4((float)y0.y, (float)(y1.y - y0.y - m0.y / 3.0 - m1.y / 6.0),
+                         (float)(0.5 * m0.y), (float)((m1.y - m0.y) / 6.0));
+      } else {
+        cr = make_float4((float)y0.x, (float)(y1.x - y0.x), 0.f, 0.f);
+        ci = make_float4((float)y0.y, (float)(y1.y - y0.y), 0.f, 0.f);
+      }
+    } else {
+      cr = make_float4((float)y[k].x, 0.f, 0.f, 0.f);
+      ci = make_float4((float)y[k].y, 0.f, 0.f, 0.f);
+    }
+    coef[(size_t)(off + k) * 2] = cr;
+    coef[(size_t)(off + k) * 2 + 1] = ci;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Oversampled kernel cache (section 4.4, Algorithm 2).  Each block writes
+// the elements [e0, e1) of one plane, e = ((fv os + fu) S + b) S + a; the
+// plane's spline intervals are staged in LDS.  Stores are coalesced
+// (consecutive lanes, consecutive elements) and non-temporal: the cache is
+// written once and read by a later consumer.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict__ units,
+                                                  const PlaneInfo* __restrict__ planes,
+                                                  const float4* __restrict__ coef, int os,
+                                                  FastDiv divOs, float q,
+                                                  float2* __restrict__ out) {
+  extern __shared__ float4 sc[];
+  const ResampleUnit u = units[blockIdx.x];
+  const PlaneInfo pi = planes[u.p];
+  const int tid = threadIdx.x;
+  const float4* src = coef + (size_t)pi.line_off * 2;
+  for (int k = tid; k < pi.nrho * 2; k += 256) sc[k] = src[k];
+  __syncthreads();
+  f32x2* o = (f32x2*)(out + pi.out_off);
+  const uint32_t S = (uint32_t)pi.S;
+  const int nmax = pi.nrho - 2;
+  for (int e = u.e0 + tid; e < u.e1; e += 256) {
+    const uint32_t R = fastdiv((uint32_t)e, pi.divS);
+    const int a = e - (int)(R * S);
+    const uint32_t F = fastdiv(R, pi.divS);
+    const int b = (int)(R - F * S);
+    const uint32_t fv = fastdiv(F, divOs);
+    const int fu = (int)(F - fv * (uint32_t)os);
+    const int X = os * (a - pi.h) - fu;
+    const int Y = os * (b - pi.h) - (int)fv;
+    const int d2 = X * X + Y * Y;
+    f32x2 v = {0.f, 0.f};
+    if (d2 <= pi.lim) {
+      const float tr = q * sqrtf((float)d2);
+      const int k = min((int)tr, nmax);
+      const float uu = tr - (float)k;
+      const float4 cr = sc[2 * k];
+      const float4 ci = sc[2 * k + 1];
+      v.x = cr.x + uu * (cr.y + uu * (cr.z + uu * cr.w));
+      v.y = ci.x + uu * (ci.y + uu * (ci.z + uu * ci.w));
+    }
+    __builtin_nontemporal_store(v, o + e);
+  }
+}
+
+// Radial lines in caller order (complex128), K-chunk partial sums combined.
+__global__ void k_lines_out(int P, int nkc, int lineTotal, const int32_t* __restrict__ perm,
+                            const int32_t* __restrict__ nrhoSorted,
+                            const int32_t* __restrict__ lineOffSorted,
+                            const int32_t* __restrict__ lineOffCaller,
+                            const double* __restrict__ part, double2* __restrict__ lines) {
+  const int j = blockIdx.y;
+  if (j >= P) return;
+  const int n = nrhoSorted[j];
+  const int so = lineOffSorted[j];
+  const int co = lineOffCaller[perm[j]];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < nkc; ++c) {
+      const double2 v = ((const double2*)part)[(size_t)c * lineTotal + so + k];
+      re += v.x;
+      im += v.y;
+    }
+    lines[co + k] = make_double2(re, im);
+  }
+}
+
+}  // namespace
+
+// ------------------------------ launchers ---------------------------------
+hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s) {
+  dim3 grid((p.NrPad + 255) / 256, p.rowsPad);
+  hipLaunchKernelGGL(k_hankel_matrix, grid, dim3(256), 0, s, p.rowsPad, p.NrPad, p.Nr,
+                     p.nrhoMax, p.dr, p.drho, p.M32, p.Msplit);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen(const DevPlan& p, const float* taper, const double* w, hipStream_t s) {
+  const int gy = p.P < 65535 ? p.P : 65535;
+  if (p.precision == 0) {
+    dim3 grid((p.NrPad + 255) / 256, gy);
+    hipLaunchKernelGGL(k_screen_f32, grid, dim3(256), 0, s, p.P, p.Nr, p.NrPad, p.perm, p.phi,
+                       taper, w, p.B32);
+  } else {
+    dim3 grid((p.NrPad / 8 + 255) / 256, gy);
+    hipLaunchKernelGGL(k_screen_bf16, grid, dim3(256), 0, s, p.P, p.Nr, p.NrPad, p.perm, p.phi,
+                       taper, w, p.Bsplit);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_contract(const DevPlan& p, hipStream_t s) {
+  if (p.nTiles == 0) return hipSuccess;
+  if (p.precision == 0) {
+    hipLaunchKernelGGL(k_contract_f32<2>, dim3(p.nTiles), dim3(64), 0, s, p.tiles, p.NrPad,
+                       p.kchunk, p.P, p.lineTotal, p.M32, p.B32, p.nrhoSorted, p.lineOffSorted,
+                       p.part);
+  } else {
+    hipLaunchKernelGGL(k_contract_bf16x6<2>, dim3(p.nTiles), dim3(64), 0, s, p.tiles, p.NrPad,
+                       p.kchunk, p.P, p.lineTotal, p.Msplit, p.Bsplit, p.nrhoSorted,
+                       p.lineOffSorted, p.part);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_spline(const DevPlan& p, hipStream_t s) {
+  const size_t shm = (size_t)3 * p.nrhoMax * sizeof(double2);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_spline,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_spline, dim3(p.P), dim3(64), shm, s, p.nkc, p.lineTotal, p.interp,
+                     p.nrhoSorted, p.lineOffSorted, p.cprime, p.part, p.coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample(const DevPlan& p, void* out, hipStream_t s) {
+  if (p.nUnits == 0) return hipSuccess;
+  const size_t shm = (size_t)2 * p.nrhoMax * sizeof(float4);
+  hipLaunchKernelGGL(k_resample, dim3(p.nUnits), dim3(256), shm, s, p.units, p.planes, p.coef,
+                     p.os, make_fastdiv((uint32_t)p.os), (float)p.q, (float2*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lines_out(const DevPlan& p, const int32_t* lineOffCaller, void* lines,
+                            hipStream_t s) {
+  const int gy = p.P;
+  dim3 grid(4, gy);
+  hipLaunchKernelGGL(k_lines_out, grid, dim3(256), 0, s, p.P, p.nkc, p.lineTotal, p.perm,
+                     p.nrhoSorted, p.lineOffSorted, lineOffCaller, p.part, (double2*)lines);
+  return hipGetLastError();
+}
+
+}  // namespace wkern

@@ -1,0 +1,274 @@
+"""Python binding of the wkern C ABI (include/wkern.h).
+
+Argument marshalling only: every step of kernel generation runs in the HIP
+library ``libwkern.so``.  PyTorch provides device memory and streams.  If the
+library has not been built, every entry point raises ``WkernError``; there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwkern.so")
+
+ABI_VERSION = 1
+PRECISION = {"fp32": 0, "bf16x6": 1}
+INTERP = {"linear": 0, "cubic": 1}
+STATUS = {
+    0: "WKERN_OK",
+    1: "WKERN_ERR_INVALID_ARG",
+    2: "WKERN_ERR_OUT_OF_MEMORY",
+    3: "WKERN_ERR_DEVICE",
+    4: "WKERN_ERR_UNSUPPORTED",
+    5: "WKERN_ERR_ABI_MISMATCH",
+}
+
+# every symbol include/wkern.h declares
+EXPORTS = (
+    "wkern_abi_version", "wkern_layout_desc", "wkern_plan", "wkern_layout",
+    "wkern_generate", "wkern_generate_radial", "wkern_grad", "wkern_set_profiling",
+    "wkern_stage_times", "wkern_destroy",
+    "wkern_strerror", "wkern_last_error",
+)
+
+
+class WkernError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        self.name = STATUS.get(status, f"status {status}")
+        super().__init__(f"{self.name}: {detail}")
+
+
+class WkernDesc(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("image_size", ctypes.c_int32),
+        ("cellsize", ctypes.c_double),
+        ("n_radial", ctypes.c_int32),
+        ("oversampling", ctypes.c_int32),
+        ("radial_refine", ctypes.c_int32),
+        ("n_planes", ctypes.c_int32),
+        ("support", ctypes.POINTER(ctypes.c_int32)),
+        ("max_support", ctypes.c_int32),
+        ("precision", ctypes.c_int),
+        ("interp", ctypes.c_int),
+        ("device", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the in-tree libwkern.so (raises WkernError if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise WkernError(3, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32p, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    desc_p = ctypes.POINTER(WkernDesc)
+    lib.wkern_abi_version.restype = ctypes.c_int32
+    lib.wkern_abi_version.argtypes = []
+    lib.wkern_layout_desc.restype = ctypes.c_int
+    lib.wkern_layout_desc.argtypes = [desc_p, i64p, i32p]
+    lib.wkern_plan.restype = ctypes.c_int
+    lib.wkern_plan.argtypes = [desc_p, ctypes.POINTER(vp)]
+    lib.wkern_layout.restype = ctypes.c_int
+    lib.wkern_layout.argtypes = [vp, i64p, i32p]
+    lib.wkern_generate.restype = ctypes.c_int
+    lib.wkern_generate.argtypes = [vp, vp, vp, vp, vp]
+    lib.wkern_generate_radial.restype = ctypes.c_int
+    lib.wkern_generate_radial.argtypes = [vp, vp, vp, vp, vp]
+    lib.wkern_grad.restype = ctypes.c_int
+    lib.wkern_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.wkern_set_profiling.restype = ctypes.c_int
+    lib.wkern_set_profiling.argtypes = [vp, ctypes.c_int32]
+    lib.wkern_stage_times.restype = ctypes.c_int
+    lib.wkern_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
+    lib.wkern_destroy.restype = ctypes.c_int
+    lib.wkern_destroy.argtypes = [vp]
+    lib.wkern_strerror.restype = ctypes.c_char_p
+    lib.wkern_strerror.argtypes = [ctypes.c_int]
+    lib.wkern_last_error.restype = ctypes.c_char_p
+    lib.wkern_last_error.argtypes = []
+    if lib.wkern_abi_version() != ABI_VERSION:
+        raise WkernError(5, f"library ABI {lib.wkern_abi_version()}, binding {ABI_VERSION}")
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise WkernError(status, load_library().wkern_last_error().decode())
+
+
+def make_desc(image_size: int, cellsize: float, n_radial: int, oversampling: int,
+              support: Sequence[int], max_support: Optional[int] = None, radial_refine: int = 1,
+              precision: str = "fp32", interp: str = "cubic", device: int = 0):
+    """Build a WkernDesc; returns (desc, support array kept alive with it)."""
+    sup = np.ascontiguousarray(np.asarray(support, dtype=np.int32))
+    if max_support is None:
+        max_support = int(sup.max()) if sup.size else 1
+    d = WkernDesc()
+    d.abi_version = ABI_VERSION
+    d.image_size = int(image_size)
+    d.cellsize = float(cellsize)
+    d.n_radial = int(n_radial)
+    d.oversampling = int(oversampling)
+    d.radial_refine = int(radial_refine)
+    d.n_planes = int(sup.shape[0])
+    d.support = sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.max_support = int(max_support)
+    d.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    d.interp = INTERP[interp] if isinstance(interp, str) else int(interp)
+    d.device = int(device)
+    return d, sup
+
+
+def layout_desc(**kw):
+    """Host-only layout (no device): returns (offsets int64 [P+1], nrho int32 [P])."""
+    lib = load_library()
+    d, sup = make_desc(**kw)
+    offs = np.zeros(d.n_planes + 1, dtype=np.int64)
+    nrho = np.zeros(d.n_planes, dtype=np.int32)
+    _check(lib.wkern_layout_desc(ctypes.byref(d),
+                                 offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 nrho.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    del sup
+    return offs, nrho
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A wkern plan (geometry, HT matrix, schedule, scratch) on one device."""
+
+    def __init__(self, image_size: int, cellsize: float, n_radial: int, oversampling: int,
+                 support: Sequence[int], max_support: Optional[int] = None,
+                 radial_refine: int = 1, precision: str = "fp32", interp: str = "cubic",
+                 device: int = 0):
+        lib = load_library()
+        d, sup = make_desc(image_size, cellsize, n_radial, oversampling, support, max_support,
+                           radial_refine, precision, interp, device)
+        h = ctypes.c_void_p()
+        _check(lib.wkern_plan(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+        self.n_planes = int(d.n_planes)
+        self.n_radial = int(n_radial)
+        self.support = sup.copy()
+        self.oversampling = int(oversampling)
+        offs = np.zeros(self.n_planes + 1, dtype=np.int64)
+        nrho = np.zeros(self.n_planes, dtype=np.int32)
+        _check(lib.wkern_layout(h, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                nrho.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        self.offsets = offs
+        self.nrho = nrho
+
+    @classmethod
+    def from_workload(cls, wl, precision: Optional[str] = None, interp: Optional[str] = None,
+                      device: int = 0) -> "Plan":
+        return cls(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, wl.support,
+                   wl.max_support, wl.radial_refine, precision or wl.precision,
+                   interp or wl.interp, device)
+
+    # ------------------------------------------------------------------
+    def _check_inputs(self, taper, w):
+        import torch
+        if taper.dtype != torch.float32 or not taper.is_cuda or taper.numel() != self.n_radial:
+            raise ValueError(f"taper must be a CUDA float32 tensor of {self.n_radial} values")
+        if w.dtype != torch.float64 or not w.is_cuda or w.numel() != self.n_planes:
+            raise ValueError(f"w must be a CUDA float64 tensor of {self.n_planes} values")
+        if not taper.is_contiguous() or not w.is_contiguous():
+            raise ValueError("taper and w must be contiguous")
+
+    def generate(self, taper, w, out=None, stream=None):
+        """Kernel cache as a flat complex64 tensor [offsets[P]] (asynchronous)."""
+        import torch
+        self._check_inputs(taper, w)
+        total = int(self.offsets[-1])
+        if out is None:
+            out = torch.empty(total, dtype=torch.complex64, device=taper.device)
+        elif out.dtype != torch.complex64 or out.numel() != total or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous complex64 tensor of {total} values")
+        _check(load_library().wkern_generate(self._h, _ptr(taper), _ptr(w), _ptr(out),
+                                             _stream_handle(stream)))
+        return out
+
+    def generate_radial(self, taper, w, out=None, stream=None):
+        """Radial lines as a flat complex128 tensor [sum nrho] (asynchronous)."""
+        import torch
+        self._check_inputs(taper, w)
+        total = int(self.nrho.sum())
+        if out is None:
+            out = torch.empty(total, dtype=torch.complex128, device=taper.device)
+        _check(load_library().wkern_generate_radial(self._h, _ptr(taper), _ptr(w), _ptr(out),
+                                                    _stream_handle(stream)))
+        return out
+
+    def grad(self, taper, w, grad_out, grad_taper=None, grad_w=None, stream=None):
+        """dL/dtau [Nr] float32 and dL/dw [P] float64 from dL/dcache (asynchronous)."""
+        import torch
+        self._check_inputs(taper, w)
+        total = int(self.offsets[-1])
+        if grad_out.dtype != torch.complex64 or grad_out.numel() != total:
+            raise ValueError("grad_out must be complex64 with the cache's size")
+        grad_out = grad_out.contiguous()
+        if grad_taper is None:
+            grad_taper = torch.empty(self.n_radial, dtype=torch.float32, device=taper.device)
+        if grad_w is None:
+            grad_w = torch.empty(self.n_planes, dtype=torch.float64, device=taper.device)
+        _check(load_library().wkern_grad(self._h, _ptr(taper), _ptr(w), _ptr(grad_out),
+                                         _ptr(grad_taper), _ptr(grad_w), _stream_handle(stream)))
+        return grad_taper, grad_w
+
+    def set_profiling(self, enable: bool):
+        _check(load_library().wkern_set_profiling(self._h, 1 if enable else 0))
+
+    STAGES = ("screen", "contraction", "spline", "resample")
+
+    def stage_times(self):
+        """(dict stage -> summed ms, number of profiled calls); waits for the events."""
+        ms = (ctypes.c_double * 4)()
+        calls = ctypes.c_int32()
+        _check(load_library().wkern_stage_times(self._h, ms, ctypes.byref(calls)))
+        return dict(zip(self.STAGES, list(ms))), calls.value
+
+    def plane_views(self, flat):
+        """Per-plane [os, os, S, S] views of a flat cache tensor."""
+        os_ = self.oversampling
+        return [flat[int(self.offsets[p]):int(self.offsets[p + 1])].view(
+            os_, os_, int(self.support[p]), int(self.support[p])) for p in range(self.n_planes)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load_library().wkern_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/wkern.h declares, validates arguments, and its layout
+agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hankel as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+lib_mod = pytest.importorskip("paper_1904_08463_amd.wkern")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lib_mod.LIB_PATH):
+        pytest.skip("libwkern.so not built")
+    return lib_mod.load_library()
+
+
+def test_header_symbols_exported(lib):
+    with open(os.path.join(ROOT, "include", "wkern.h")) as f:
+        hdr = f.read()
+    declared = set(re.findall(r"^\S[^\n(]*?\b(wkern_[a-z_]+)\s*\(", hdr, flags=re.M))
+    assert declared == set(lib_mod.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_abi_version(lib):
+    assert lib.wkern_abi_version() == lib_mod.ABI_VERSION
+
+
+@pytest.mark.parametrize("wl", [W.plain(), W.paper(), W.random_small(3, os_=5)], ids=lambda w: w.name)
+def test_layout_matches_oracle(lib, wl):
+    offs, nrho = lib_mod.layout_desc(image_size=wl.image_size, cellsize=wl.cellsize,
+                                     n_radial=wl.n_radial, oversampling=wl.oversampling,
+                                     support=wl.support, max_support=wl.max_support,
+                                     radial_refine=wl.radial_refine)
+    assert np.array_equal(offs, H.offsets(wl.support, wl.oversampling))
+    assert np.array_equal(nrho, H.n_rho(wl.support, wl.oversampling, wl.radial_refine))
+
+
+def test_layout_batch_size(lib):
+    wl = W.batch()
+    offs, _ = lib_mod.layout_desc(image_size=wl.image_size, cellsize=wl.cellsize,
+                                  n_radial=wl.n_radial, oversampling=wl.oversampling,
+                                  support=wl.support, max_support=wl.max_support)
+    # 16384 kernels of 7..255 px at os 8: 30.6 GB of complex64
+    assert abs(offs[-1] * 8 / 1e9 - 30.6) < 0.1
+
+
+BAD = [
+    ("image_size", 0), ("cellsize", 0.0), ("cellsize", float("nan")), ("cellsize", 0.02),
+    ("n_radial", 0), ("oversampling", 0), ("oversampling", 65), ("radial_refine", 0),
+    ("max_support", 4), ("precision", 7), ("interp", 3),
+]
+
+
+@pytest.mark.parametrize("field,value", BAD)
+def test_invalid_arguments(lib, field, value):
+    d, sup = lib_mod.make_desc(image_size=128, cellsize=7.8125e-4, n_radial=64, oversampling=4,
+                               support=[7, 9], max_support=9)
+    setattr(d, field, value)
+    offs = np.zeros(3, dtype=np.int64)
+    st = lib.wkern_layout_desc(ctypes.byref(d), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               None)
+    assert st == 1, (field, value, lib.wkern_last_error())
+    assert lib.wkern_last_error().decode()
+
+
+@pytest.mark.parametrize("support", [[8], [11], [0], [-3]])
+def test_invalid_supports(lib, support):
+    with pytest.raises(lib_mod.WkernError) as ei:
+        lib_mod.layout_desc(image_size=128, cellsize=7.8125e-4, n_radial=64, oversampling=4,
+                            support=support, max_support=9)
+    assert ei.value.status == 1
+
+
+def test_abi_mismatch(lib):
+    d, sup = lib_mod.make_desc(image_size=128, cellsize=7.8125e-4, n_radial=64, oversampling=4,
+                               support=[7])
+    d.abi_version = 99
+    offs = np.zeros(2, dtype=np.int64)
+    assert lib.wkern_layout_desc(ctypes.byref(d), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 None) == 5
+
+
+def test_null_arguments(lib):
+    assert lib.wkern_layout_desc(None, None, None) == 1
+    assert lib.wkern_plan(None, None) == 1
+    assert lib.wkern_generate(None, None, None, None, None) == 1
+    assert lib.wkern_grad(None, None, None, None, None, None, None) == 1
+    assert lib.wkern_destroy(None) == 0
+    for s in range(6):
+        assert lib.wkern_strerror(s)
+
+
+def test_radial_line_limit(lib):
+    # q os h + 4 beyond the spline's capacity is rejected up front
+    with pytest.raises(lib_mod.WkernError):
+        lib_mod.layout_desc(image_size=128, cellsize=7.8125e-4, n_radial=64, oversampling=16,
+                            support=[255], max_support=255, radial_refine=2)
+
+
+def test_plan_without_device_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    with pytest.raises(lib_mod.WkernError) as ei:
+        lib_mod.Plan(128, 7.8125e-4, 64, 4, [7])
+    assert ei.value.status == 3

@@ -1,0 +1,182 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Error metric per plane: e = max |K_gpu - K_ref| / max |K_ref| over the plane's
+radial line or its whole kernel cache.  Gates: FP32 contraction <= 1e-5,
+split-BF16 contraction <= 1e-6 (both are the accuracy targets of the two
+arithmetic paths); layout, zeros outside the circular support and the
+conjugate symmetry in w are checked exactly.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hankel as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GATE = {"fp32": 1e-5, "bf16x6": 1e-6}
+
+
+def _plan(wl, precision=None, interp=None):
+    from paper_1904_08463_amd import Plan
+    return Plan.from_workload(wl, precision=precision, interp=interp)
+
+
+def _inputs(wl):
+    taper = torch.from_numpy(np.ascontiguousarray(wl.taper)).cuda()
+    w = torch.from_numpy(np.ascontiguousarray(wl.w)).cuda()
+    return taper, w
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _check_cache(plan, flat_cpu, wl, planes, ref_caches, gate, tag):
+    worst = 0.0
+    for j, p in enumerate(planes):
+        o0, o1 = int(plan.offsets[p]), int(plan.offsets[p + 1])
+        got = flat_cpu[o0:o1].reshape(ref_caches[j].shape)
+        ref = ref_caches[j]
+        # exactly zero outside the circular support
+        _, mask, _ = H.sample_positions(int(wl.support[p]), wl.oversampling, wl.radial_refine)
+        assert np.all(got[~mask] == 0), f"{tag}: plane {p} nonzero outside support"
+        e = _rel(got, ref)
+        worst = max(worst, e)
+        assert e <= gate, f"{tag}: plane {p} (w={wl.w[p]:.3f}, S={wl.support[p]}) error {e:.3e} > {gate}"
+    print(f"{tag}: worst cache error {worst:.3e} over {len(planes)} planes", flush=True)
+    return worst
+
+
+def _check_lines(plan, lines_cpu, wl, planes, ref_lines, gate, tag):
+    offs = np.concatenate([[0], np.cumsum(plan.nrho)])
+    worst = 0.0
+    for j, p in enumerate(planes):
+        got = lines_cpu[offs[p]:offs[p + 1]]
+        e = _rel(got, ref_lines[j])
+        worst = max(worst, e)
+        assert e <= gate, f"{tag}: plane {p} radial error {e:.3e} > {gate}"
+    print(f"{tag}: worst radial error {worst:.3e}", flush=True)
+    return worst
+
+
+def _run_full(wl, precision, interp=None, planes=None):
+    interp = interp or wl.interp
+    print(f"case {wl.name} precision={precision} interp={interp} P={wl.n_planes} Nr={wl.n_radial}",
+          flush=True)
+    plan = _plan(wl, precision, interp)
+    taper, w = _inputs(wl)
+    lines = plan.generate_radial(taper, w).cpu().numpy()
+    flat = plan.generate(taper, w).cpu().numpy()
+    torch.cuda.synchronize()
+    planes = list(range(wl.n_planes)) if planes is None else list(planes)
+    caches, ref_lines = H.generate_workload(wl, planes=planes, interp=interp)
+    _check_lines(plan, lines, wl, planes, ref_lines, GATE[precision], f"{wl.name}/{precision}")
+    worst = _check_cache(plan, flat, wl, planes, caches, GATE[precision], f"{wl.name}/{precision}")
+    plan.close()
+    return worst
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_plain_workload(precision):
+    _run_full(W.plain(), precision)
+
+
+def test_precision_workload_bf16x6():
+    """Plain workload through the split-BF16 contraction, FP64 phase: <= 1e-6."""
+    _run_full(W.precision(), "bf16x6")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_linear_interpolation(precision):
+    _run_full(W.plain(), precision, interp="linear")
+
+
+@pytest.mark.parametrize("q", [2, 4])
+def test_radial_refinement(q):
+    _run_full(W.plain(radial_refine=q), "bf16x6")
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_random_ragged(seed, precision):
+    """Ragged radial lengths, Nr not a multiple of the tile sizes, odd and even
+    oversampling, supports down to 1."""
+    os_ = [1, 3, 4, 7][seed - 1]
+    wl = W.random_small(seed, n_planes=37, n_radial=[96, 333, 64, 1000][seed - 1], os_=os_,
+                        max_support=[21, 15, 33, 9][seed - 1])
+    _run_full(wl, precision)
+
+
+def test_single_plane_support_one():
+    wl = W.random_small(9, n_planes=1, n_radial=50, os_=2, max_support=1)
+    _run_full(wl, "fp32")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_conjugate_symmetry_and_determinism(precision):
+    """K(-w) = conj K(w) (section 4.1), and two generations of the same plan
+    agree bit for bit.  The FP32 matrix-core sums are sign-symmetric, so the
+    FP32 path is conjugate bit for bit; the BF16 matrix-core sums are not, so
+    the split path is held to its accuracy gate."""
+    wl = W.plain(extra_w=[-v for v in W.plain().w])
+    plan = _plan(wl, precision)
+    taper, w = _inputs(wl)
+    a = plan.generate(taper, w).cpu().numpy()
+    b = plan.generate(taper, w).cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    for p in range(8):
+        pos = a[plan.offsets[p]:plan.offsets[p + 1]]
+        neg = a[plan.offsets[p + 8]:plan.offsets[p + 9]]
+        if precision == "fp32":
+            assert np.array_equal(neg, np.conj(pos))
+        else:
+            e = _rel(neg, np.conj(pos))
+            print(f"plane {p}: |K(-w) - conj K(w)| / max = {e:.3e}", flush=True)
+            assert e <= GATE[precision]
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_paper_workload_sampled_planes(precision):
+    """2048^2 at 3.5 arcsec, 256 planes, Nr 4096, os 8, S 7..127: oracle on a
+    spread of planes covering the support range."""
+    wl = W.paper()
+    planes = sorted(set([0, 1, 2, 40, 85, 128, 170, 200, 230, 254, 255]))
+    _run_full(wl, precision, planes=planes)
+
+
+def _batch_planes(wl, n=24):
+    # stratified: every channel's extreme, several supports, both signs
+    order = np.argsort(wl.support, kind="stable")
+    pick = set(order[np.linspace(0, len(order) - 1, n).astype(int)].tolist())
+    pick |= {0, 511, 512, 1023, 15 * 1024, 15 * 1024 + 1023}
+    return sorted(pick)
+
+
+@pytest.mark.parametrize("precision", ["bf16x6", "fp32"])
+def test_batch_workload_full_size(precision):
+    """16 channels x 1024 w-planes, Nr 8192, os 8, S 7..255, all 16384 kernels in
+    one generate call (the benchmark's launch); oracle on a stratified subset."""
+    wl = W.batch(precision=precision)
+    planes = _batch_planes(wl)
+    print(f"case batch precision={precision} planes={planes}", flush=True)
+    plan = _plan(wl, precision)
+    taper, w = _inputs(wl)
+    flat = plan.generate(taper, w)
+    torch.cuda.synchronize()
+    got = {}
+    for p in planes:
+        got[p] = flat[int(plan.offsets[p]):int(plan.offsets[p + 1])].cpu().numpy()
+    del flat
+    caches, _ = H.generate_workload(wl, planes=planes)
+    worst = 0.0
+    for j, p in enumerate(planes):
+        ref = caches[j]
+        e = _rel(got[p].reshape(ref.shape), ref)
+        worst = max(worst, e)
+        assert e <= GATE[precision], f"plane {p} S={wl.support[p]} w={wl.w[p]:.1f}: {e:.3e}"
+    print(f"batch/{precision}: worst error {worst:.3e} over {len(planes)} planes", flush=True)
+    plan.close()
