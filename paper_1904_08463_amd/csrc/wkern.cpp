@@ -129,6 +129,7 @@ struct wkern_plan_s {
   std::vector<int64_t> offsets;       // [P + 1]
   std::vector<int32_t> nrho;          // [P] caller order
   std::vector<int32_t> lineOffCaller; // [P + 1]
+  std::vector<int32_t> nrhoSorted;    // [P] longest first
   DevPlan dp{};
   int32_t* d_lineOffCaller = nullptr;
   std::vector<void*> allocations;
@@ -249,6 +250,8 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   }
   pl->lineOffCaller[P] = (int32_t)acc;
 
+  pl->nrhoSorted = nrhoSorted;
+  g.nrhoSortedHost = pl->nrhoSorted.data();
   g.nrhoMax = nrhoSorted[0];
   g.rowsPad = (int)round_up(g.nrhoMax, kRowAlign);
   g.colsPad = (int)round_up(2 * (int64_t)P, kColAlign);
@@ -259,18 +262,34 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   g.nkc = g.NrPad / g.kchunk;
 
   // contraction tiles: 32 rows x 64 columns (32 planes) per wave, staircase
-  // over the sorted planes: a column block needs the rows of its longest line
-  std::vector<Tile> tiles;
+  // over the sorted planes: a column block needs the rows of its longest line.
+  // Tiles that read the same screen columns over the same K-chunk form a
+  // group; a group is pinned to one XCD (workgroup i runs on XCD i % 8) and
+  // its tiles are dispatched back to back there, so the group's slice of the
+  // screen is read from HBM once and then served by that XCD's L2.
+  std::vector<std::vector<Tile>> xcdQueue(kNumXcd);
   const int colTile = 64;
+  int group = 0;
   for (int c0 = 0; c0 < 2 * P; c0 += colTile) {
     const int rows = nrhoSorted[c0 / 2];
-    for (int r0 = 0; r0 < rows; r0 += 32)
-      for (int kc = 0; kc < g.nkc; ++kc) tiles.push_back(Tile{r0, c0, kc * g.kchunk, kc});
+    for (int kc = 0; kc < g.nkc; ++kc, ++group) {
+      std::vector<Tile>& q = xcdQueue[group % kNumXcd];
+      for (int r0 = 0; r0 < rows; r0 += 32) q.push_back(Tile{r0, c0, kc * g.kchunk, kc});
+    }
   }
+  std::vector<Tile> tiles;
+  size_t longest = 0;
+  for (auto& q : xcdQueue) longest = std::max(longest, q.size());
+  // interleave the per-XCD queues; a short queue is padded by repeating its
+  // last tile index as a no-op marker (row0 = -1)
+  for (size_t m = 0; m < longest; ++m)
+    for (int x = 0; x < kNumXcd; ++x)
+      tiles.push_back(m < xcdQueue[x].size() ? xcdQueue[x][m] : Tile{-1, 0, 0, 0});
   g.nTiles = (int)tiles.size();
 
-  // resample units: blocks of at most 16384 elements of one plane
-  const int64_t unitElems = 16384;
+  // resample units: blocks of at most 65536 elements of one plane (multiples of
+  // 256, so every wave chunk starts 64-aligned)
+  const int64_t unitElems = 65536;
   std::vector<ResampleUnit> units;
   std::vector<PlaneInfo> planes(P);
   const int os = d->oversampling;
@@ -283,8 +302,7 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
     pi.S = S;
     pi.h = (S - 1) / 2;
     pi.lim = (os * pi.h) * (os * pi.h);
-    pi.pad = 0;
-    pi.divS = make_fastdiv((uint32_t)S);
+    pi.invS = 1.0f / (float)S;
     const int64_t n = (int64_t)os * os * S * S;
     for (int64_t e0 = 0; e0 < n; e0 += unitElems)
       units.push_back(ResampleUnit{p, (int32_t)e0, (int32_t)std::min(n, e0 + unitElems), 0});

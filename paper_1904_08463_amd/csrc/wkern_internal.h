@@ -17,23 +17,12 @@ constexpr int kRowAlign = 128;
 constexpr int kColAlign = 128;
 // Largest radial line a plane may have (sets the spline's LDS footprint).
 constexpr int kMaxRho = 2048;
+// Accelerator complex dies (XCDs) of an MI355X; consecutive workgroups are
+// dispatched round-robin over them.
+constexpr int kNumXcd = 8;
 // Warm-up length of the truncated spline recurrences; the neglected start
 // value is damped by (2 - sqrt 3)^32 ~ 5e-19.
 constexpr int kSplineWarm = 32;
-
-// Exact division of n < 2^24 by d < 2^16 with one 64-bit multiply:
-// q = (n * m) >> 40, m = floor(2^40 / d) + 1.
-struct FastDiv {
-  uint64_t m;
-  uint32_t d;
-};
-
-inline FastDiv make_fastdiv(uint32_t d) {
-  FastDiv f;
-  f.d = d;
-  f.m = ((uint64_t)1 << 40) / d + 1;
-  return f;
-}
 
 // Per-plane table used by the resampler (caller order).
 struct PlaneInfo {
@@ -43,8 +32,7 @@ struct PlaneInfo {
   int32_t S;          // full width
   int32_t h;          // half width
   int32_t lim;        // (os h)^2
-  int32_t pad;
-  FastDiv divS;
+  float invS;         // 1 / S (estimate for the exact small division)
 };
 
 // One block of output elements [e0, e1) of plane p (plane-local indices).
@@ -56,7 +44,8 @@ struct ResampleUnit {
 };
 
 // One contraction tile: rows [row0, row0 + rows), sorted columns
-// [col0, col0 + cols), radial nodes [k0, k1).
+// [col0, col0 + cols), radial nodes [k0, k0 + kchunk).  row0 < 0 marks a
+// padding entry that does nothing.
 struct Tile {
   int32_t row0;
   int32_t col0;
@@ -78,6 +67,7 @@ struct DevPlan {
   int32_t* nrhoSorted;    // [P]
   int32_t* lineOffSorted; // [P + 1]
   double* cprime;         // [nrhoMax] Thomas coefficients
+  const int32_t* nrhoSortedHost;  // [P] host copy of nrhoSorted
   PlaneInfo* planes;      // [P] caller order
   Tile* tiles;
   int nTiles;

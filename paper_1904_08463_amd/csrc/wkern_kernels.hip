@@ -36,10 +36,6 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
-__device__ __forceinline__ uint32_t fastdiv(uint32_t n, FastDiv f) {
-  return (uint32_t)(((uint64_t)n * f.m) >> 40);
-}
-
 // --------------------------------------------------------------------------
 // Discrete HT matrix (section 4.3): M[k, i] = 2 pi J0(2 pi rho_k r_i) r_i dr,
 // midpoint nodes r_i = (i + 1/2) dr, rho_k = k drho.  FP64 with the device
@@ -193,6 +189,7 @@ __global__ __launch_bounds__(64) void k_contract_f32(
     const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
     double* __restrict__ part) {
   const Tile t = tiles[blockIdx.x];
+  if (t.row0 < 0) return;
   const int lane = threadIdx.x;
   const int hb = lane >> 5;
   const int rr = lane & 31;
@@ -244,6 +241,7 @@ __global__ __launch_bounds__(64) void k_contract_bf16x6(
     const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
     double* __restrict__ part) {
   const Tile t = tiles[blockIdx.x];
+  if (t.row0 < 0) return;
   const int lane = threadIdx.x;
   const int hb = lane >> 5;
   const int rr = lane & 31;
@@ -314,14 +312,14 @@ __global__ __launch_bounds__(64) void k_contract_bf16x6(
 // Output per interval k: power-form coefficients c0..c3 of re and im,
 //   s(k + u) = c0 + u (c1 + u (c2 + u c3)),  u in [0, 1).
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_spline(int nkc, int lineTotal, int interp,
+__global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, int interp,
                                                const int32_t* __restrict__ nrhoSorted,
                                                const int32_t* __restrict__ lineOffSorted,
                                                const double* __restrict__ cprime,
                                                const double* __restrict__ part,
                                                float4* __restrict__ coef) {
   extern __shared__ double2 smem[];
-  const int j = blockIdx.x;
+  const int j = j0 + blockIdx.x;
   const int lane = threadIdx.x;
   const int n = nrhoSorted[j];
   const int off = lineOffSorted[j];
@@ -415,43 +413,129 @@ __global__ __launch_bounds__(64) void k_spline(int nkc, int lineTotal, int inter
 // plane's spline intervals are staged in LDS.  Stores are coalesced
 // (consecutive lanes, consecutive elements) and non-temporal: the cache is
 // written once and read by a later consumer.
+//
+// Radius in units of the radial node spacing: t = q sqrt(d2), d2 = X^2 + Y^2
+// (an integer, exact in FP32).  Rounding t itself to FP32 would cost up to
+// ulp(t) ~ 6e-5 nodes at t ~ 1000; instead sqrt(d2) = s + c with s from the
+// hardware reciprocal square root and the Newton correction
+// c = (d2 - s^2) / (2 s) formed with an exact fma residual, and the interval
+// fraction u = (q s - k) + q c keeps ~1e-7 absolute accuracy.  k is the
+// truncation of q s: a value that lands one node early or late only moves
+// u slightly outside [0, 1), where the neighbouring cubic piece agrees.
 // --------------------------------------------------------------------------
+__device__ __forceinline__ f32x2 cache_value(int X, int Y, int lim, float q, int nmax,
+                                             const float4* __restrict__ sc) {
+  const int d2 = X * X + Y * Y;
+  f32x2 v = {0.f, 0.f};
+  if (d2 <= lim) {
+    const float d2f = (float)d2;
+    const float r = __builtin_amdgcn_rsqf(d2f);
+    const bool nz = d2 > 0;
+    const float sq = nz ? d2f * r : 0.f;
+    const float res = fmaf(-sq, sq, d2f);
+    const float corr = nz ? 0.5f * res * r : 0.f;
+    const int k = min((int)(q * sq), nmax);
+    const float uu = fmaf(q, corr, fmaf(q, sq, -(float)k));
+    const float4 cr = sc[2 * k];
+    const float4 ci = sc[2 * k + 1];
+    v.x = fmaf(uu, fmaf(uu, fmaf(uu, cr.w, cr.z), cr.y), cr.x);
+    v.y = fmaf(uu, fmaf(uu, fmaf(uu, ci.w, ci.z), ci.y), ci.x);
+  }
+  return v;
+}
+
+// Exact n / d for n < 2^24 and d < 2^16 from an FP32 reciprocal estimate
+// (off by at most one) and one integer correction.
+__device__ __forceinline__ int div_small(int n, int d, float inv, int& rem) {
+  int qt = (int)((float)n * inv);
+  int r = n - qt * d;
+  if (r < 0) {
+    qt -= 1;
+    r += d;
+  } else if (r >= d) {
+    qt += 1;
+    r -= d;
+  }
+  rem = r;
+  return qt;
+}
+
 __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict__ units,
                                                   const PlaneInfo* __restrict__ planes,
                                                   const float4* __restrict__ coef, int os,
-                                                  FastDiv divOs, float q,
+                                                  float invOs, float q,
                                                   float2* __restrict__ out) {
   extern __shared__ float4 sc[];
   const ResampleUnit u = units[blockIdx.x];
   const PlaneInfo pi = planes[u.p];
-  const int tid = threadIdx.x;
   const float4* src = coef + (size_t)pi.line_off * 2;
-  for (int k = tid; k < pi.nrho * 2; k += 256) sc[k] = src[k];
+  for (int k = threadIdx.x; k < pi.nrho * 2; k += 256) sc[k] = src[k];
   __syncthreads();
   f32x2* o = (f32x2*)(out + pi.out_off);
-  const uint32_t S = (uint32_t)pi.S;
+  const int S = pi.S;
+  const int h = pi.h;
   const int nmax = pi.nrho - 2;
-  for (int e = u.e0 + tid; e < u.e1; e += 256) {
-    const uint32_t R = fastdiv((uint32_t)e, pi.divS);
-    const int a = e - (int)(R * S);
-    const uint32_t F = fastdiv(R, pi.divS);
-    const int b = (int)(R - F * S);
-    const uint32_t fv = fastdiv(F, divOs);
-    const int fu = (int)(F - fv * (uint32_t)os);
-    const int X = os * (a - pi.h) - fu;
-    const int Y = os * (b - pi.h) - (int)fv;
-    const int d2 = X * X + Y * Y;
-    f32x2 v = {0.f, 0.f};
-    if (d2 <= pi.lim) {
-      const float tr = q * sqrtf((float)d2);
-      const int k = min((int)tr, nmax);
-      const float uu = tr - (float)k;
-      const float4 cr = sc[2 * k];
-      const float4 ci = sc[2 * k + 1];
-      v.x = cr.x + uu * (cr.y + uu * (cr.z + uu * cr.w));
-      v.y = ci.x + uu * (ci.y + uu * (ci.z + uu * ci.w));
+  const int lane = threadIdx.x & 63;
+  if (S >= 64) {
+    // Each wave takes 64-element chunks wave, wave + 4, ...; the chunk's first
+    // element is decoded once (wave-uniform) and advanced by 256 elements per
+    // step; within a chunk a row boundary is crossed at most once.
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int e = u.e0 + 64 * wave;
+    int R = e / S;
+    int a0 = e - R * S;
+    int F = R / S;
+    int b0 = R - F * S;
+    int fv0 = F / os;
+    int fu0 = F - fv0 * os;
+    const int stepA = 256 % S;
+    const int stepR = 256 / S;
+    for (; e < u.e1; e += 256) {
+      if (e + lane < u.e1) {
+        int a = a0 + lane;
+        int b = b0, fu = fu0, fv = fv0;
+        if (a >= S) {
+          a -= S;
+          b += 1;
+          if (b == S) {
+            b = 0;
+            fu += 1;
+            if (fu == os) {
+              fu = 0;
+              fv += 1;
+            }
+          }
+        }
+        const int X = os * (a - h) - fu;
+        const int Y = os * (b - h) - fv;
+        __builtin_nontemporal_store(cache_value(X, Y, pi.lim, q, nmax, sc), o + e + lane);
+      }
+      a0 += stepA;
+      int c = stepR;
+      if (a0 >= S) {
+        a0 -= S;
+        c += 1;
+      }
+      b0 += c;
+      if (b0 >= S) {
+        b0 -= S;
+        fu0 += 1;
+        if (fu0 == os) {
+          fu0 = 0;
+          fv0 += 1;
+        }
+      }
     }
-    __builtin_nontemporal_store(v, o + e);
+  } else {
+    for (int e = u.e0 + (int)threadIdx.x; e < u.e1; e += 256) {
+      int a, b, fu;
+      const int R = div_small(e, S, pi.invS, a);
+      const int F = div_small(R, S, pi.invS, b);
+      const int fv = div_small(F, os, invOs, fu);
+      const int X = os * (a - h) - fu;
+      const int Y = os * (b - h) - fv;
+      __builtin_nontemporal_store(cache_value(X, Y, pi.lim, q, nmax, sc), o + e);
+    }
   }
 }
 
@@ -516,22 +600,38 @@ hipError_t launch_contract(const DevPlan& p, hipStream_t s) {
 }
 
 hipError_t launch_spline(const DevPlan& p, hipStream_t s) {
-  const size_t shm = (size_t)3 * p.nrhoMax * sizeof(double2);
-  if (shm > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_spline,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  // Planes are sorted by radial length (longest first); each launch covers a
+  // run of planes whose lines fit its LDS size, so short lines are not
+  // limited to the occupancy of the longest one.
+  static const int kBucket[] = {kMaxRho, 512, 128, 48};
+  int j0 = 0;
+  for (int b = 0; b < 4 && j0 < p.P; ++b) {
+    const int cap = kBucket[b];
+    const int nextCap = b + 1 < 4 ? kBucket[b + 1] : 0;
+    int j1 = j0;
+    while (j1 < p.P && p.nrhoSortedHost[j1] > nextCap) ++j1;
+    if (j1 == j0) continue;
+    const int nmax = p.nrhoSortedHost[j0] < cap ? p.nrhoSortedHost[j0] : cap;
+    const size_t shm = (size_t)3 * nmax * sizeof(double2);
+    if (shm > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_spline,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_spline, dim3(j1 - j0), dim3(64), shm, s, j0, p.nkc, p.lineTotal,
+                       p.interp, p.nrhoSorted, p.lineOffSorted, p.cprime, p.part, p.coef);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    j0 = j1;
   }
-  hipLaunchKernelGGL(k_spline, dim3(p.P), dim3(64), shm, s, p.nkc, p.lineTotal, p.interp,
-                     p.nrhoSorted, p.lineOffSorted, p.cprime, p.part, p.coef);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_resample(const DevPlan& p, void* out, hipStream_t s) {
   if (p.nUnits == 0) return hipSuccess;
   const size_t shm = (size_t)2 * p.nrhoMax * sizeof(float4);
   hipLaunchKernelGGL(k_resample, dim3(p.nUnits), dim3(256), shm, s, p.units, p.planes, p.coef,
-                     p.os, make_fastdiv((uint32_t)p.os), (float)p.q, (float2*)out);
+                     p.os, 1.0f / (float)p.os, (float)p.q, (float2*)out);
   return hipGetLastError();
 }
 
