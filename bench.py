@@ -121,17 +121,28 @@ def main():
 
     res_ms = stages["resample"]
     achieved = out_bytes / (res_ms * 1e-3) / 1e9
+    info = plan.info()
     paths = {"bf16x6": {"kernels_per_s": value, "ms_per_step": ms,
-                        "stage_ms": stages, "max_rel_err_sampled": err_bf16}}
+                        "stage_ms": stages, "max_rel_err_sampled": err_bf16,
+                        "pipeline_chunks": info["chunks"], "contraction_variant": info["variant"],
+                        "autotune_ms": info["variant_ms"]}}
+    # the same plan with the stages run one after the other (no overlap)
+    plan.set_chunks(1)
+    wall1, stages1 = _time_path(plan, taper, w, out, args.steps, 1)
+    paths["bf16x6_serial"] = {"kernels_per_s": wl.n_planes / (wall1 / args.steps),
+                              "ms_per_step": 1000.0 * wall1 / args.steps, "stage_ms": stages1}
     plan.close()
 
     if not args.skip_fp32:
         plan32 = Plan.from_workload(wl, precision="fp32")
         wall32, stages32 = _time_path(plan32, taper, w, out, args.steps, args.warmup)
         err32 = _sampled_error(plan32, out, wl, check_planes)
+        info32 = plan32.info()
         paths["fp32"] = {"kernels_per_s": wl.n_planes / (wall32 / args.steps),
                          "ms_per_step": 1000.0 * wall32 / args.steps, "stage_ms": stages32,
-                         "max_rel_err_sampled": err32}
+                         "max_rel_err_sampled": err32, "pipeline_chunks": info32["chunks"],
+                         "contraction_variant": info32["variant"],
+                         "autotune_ms": info32["variant_ms"]}
         plan32.close()
 
     line = {

@@ -156,6 +156,27 @@ wkern_status wkern_set_profiling(wkern_plan_t plan, int32_t enable);
  * (calls: host, may be NULL).  Errors: INVALID_ARG, DEVICE. */
 wkern_status wkern_stage_times(wkern_plan_t plan, double* ms, int32_t* calls);
 
+/* Tuning state of a plan.  variant: the Hankel-contraction kernel variant
+ * the plan-time autotuner chose (it times every candidate on the plan's own
+ * tile lists); n_variants: number of candidates; variant_ms: host float
+ * [n_variants], the measured time of each (may be NULL); chunks: number of
+ * pipeline chunks (the resample of one chunk of planes overlaps the screen,
+ * contraction and spline of the next).  Any output pointer may be NULL.
+ * Errors: INVALID_ARG. */
+wkern_status wkern_plan_info(wkern_plan_t plan, int32_t* variant, int32_t* n_variants,
+                             float* variant_ms, int32_t* chunks);
+
+/* Override the autotuner's choice of contraction variant (0 <= variant <
+ * n_variants).  All variants compute the same sums in the same order per
+ * output element.  Errors: INVALID_ARG. */
+wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant);
+
+/* Re-split the batch into `chunks` pipeline chunks of about equal cache
+ * size (clamped to the number of planes; 1 = the stages run one after the
+ * other on the caller's stream).  Synchronous: waits for the plan's device
+ * first.  Errors: INVALID_ARG (chunks < 1), DEVICE, OUT_OF_MEMORY. */
+wkern_status wkern_set_chunks(wkern_plan_t plan, int32_t chunks);
+
 /* Release the plan and everything it owns.  Synchronises the plan's device
  * first.  NULL is accepted and ignored. */
 wkern_status wkern_destroy(wkern_plan_t plan);

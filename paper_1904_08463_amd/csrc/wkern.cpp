@@ -123,6 +123,13 @@ struct DeviceGuard {
 
 }  // namespace
 
+// One profiled launch: stage index and the events around it.
+struct StageRecord {
+  int stage;
+  hipEvent_t start;
+  hipEvent_t end;
+};
+
 struct wkern_plan_s {
   wkern_desc desc{};
   std::vector<int32_t> support;
@@ -130,17 +137,42 @@ struct wkern_plan_s {
   std::vector<int32_t> nrho;          // [P] caller order
   std::vector<int32_t> lineOffCaller; // [P + 1]
   std::vector<int32_t> nrhoSorted;    // [P] longest first
+  std::vector<int32_t> perm;          // [P] sorted j -> caller p
   DevPlan dp{};
   int32_t* d_lineOffCaller = nullptr;
   std::vector<void*> allocations;
-  // stage profiling: one set of 5 events per profiled generate call
+
+  // pipeline chunks over the sorted planes
+  int nChunks = 1;
+  std::vector<int> chunkJ;   // [C + 1] sorted-plane boundaries
+  std::vector<int> chunkU;   // [C + 1] resample-unit boundaries
+  // contraction tile lists, one per variant, ordered by chunk
+  Tile* d_tiles[kNumVariants] = {};
+  std::vector<int> chunkT[kNumVariants];  // [C + 1] tile boundaries
+  int variant = kWave32x64;
+  float variantMs[kNumVariants] = {};
+  // internal streams (default priority) and their synchronisation
+  hipStream_t sCompute = nullptr, sStore = nullptr;
+  hipEvent_t evFork = nullptr, evJoinCompute = nullptr, evJoinStore = nullptr;
+  std::vector<hipEvent_t> evChunk;  // [C] compute of chunk c finished
+
+  // stage profiling
   bool profiling = false;
-  std::vector<std::array<hipEvent_t, 5>> events;
-  size_t eventsUsed = 0;
+  int profiledCalls = 0;
+  std::vector<StageRecord> records;
+  size_t recordsUsed = 0;
 
   ~wkern_plan_s() {
-    for (auto& ev : events)
-      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (auto& r : records) {
+      (void)hipEventDestroy(r.start);
+      (void)hipEventDestroy(r.end);
+    }
+    for (hipEvent_t e : evChunk) (void)hipEventDestroy(e);
+    if (evFork) (void)hipEventDestroy(evFork);
+    if (evJoinCompute) (void)hipEventDestroy(evJoinCompute);
+    if (evJoinStore) (void)hipEventDestroy(evJoinStore);
+    if (sCompute) (void)hipStreamDestroy(sCompute);
+    if (sStore) (void)hipStreamDestroy(sStore);
     for (void* ptr : allocations) (void)hipFree(ptr);
   }
 
@@ -159,13 +191,101 @@ struct wkern_plan_s {
   }
 
   template <class T>
+  void release(T*& ptr) {
+    if (!ptr) return;
+    auto it = std::find(allocations.begin(), allocations.end(), (void*)ptr);
+    if (it != allocations.end()) allocations.erase(it);
+    (void)hipFree((void*)ptr);
+    ptr = nullptr;
+  }
+
+  template <class T>
   wkern_status upload(T** ptr, const std::vector<T>& host, const char* what) {
     wkern_status s = alloc(ptr, host.size(), what);
     if (s != WKERN_OK) return s;
     WK_HIP(hipMemcpy(*ptr, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice), what);
     return WKERN_OK;
   }
+
+  // Event pair for one profiled launch (pooled across calls).
+  wkern_status record_begin(int stage, hipStream_t st, StageRecord** rec) {
+    *rec = nullptr;
+    if (!profiling) return WKERN_OK;
+    if (recordsUsed == records.size()) {
+      StageRecord r{stage, nullptr, nullptr};
+      WK_HIP(hipEventCreate(&r.start), "hipEventCreate");
+      WK_HIP(hipEventCreate(&r.end), "hipEventCreate");
+      records.push_back(r);
+    }
+    StageRecord* r = &records[recordsUsed++];
+    r->stage = stage;
+    WK_HIP(hipEventRecord(r->start, st), "hipEventRecord");
+    *rec = r;
+    return WKERN_OK;
+  }
 };
+
+namespace {
+
+wkern_status record_end(StageRecord* r, hipStream_t st) {
+  if (r) WK_HIP(hipEventRecord(r->end, st), "hipEventRecord");
+  return WKERN_OK;
+}
+
+// Tiles of one contraction variant over sorted planes [j0, j1): column
+// blocks of the variant's width start at the chunk's first plane (the last
+// block of a chunk stops at j1: tiles carry the chunk end and never store
+// columns beyond it), row tiles of 32 * rb cover the block's longest line.
+// Tiles that read the same screen columns over the same K-chunk form a
+// group; a group is pinned to one XCD (workgroup i runs on XCD i % 8) and its
+// tiles are dispatched back to back there, so the group's slice of the
+// screen is read from HBM once and then served by that XCD's L2.
+void build_tiles(int variant, int j0, int j1, const std::vector<int32_t>& nrhoSorted, int nkc,
+                 int kchunk, std::vector<Tile>& out) {
+  const ContractShape sh = contract_shape(variant);
+  const int rowTile = 32 * sh.rb;
+  std::vector<std::vector<Tile>> xcdQueue(kNumXcd);
+  int group = 0;
+  for (int c0 = 2 * j0; c0 < 2 * j1; c0 += sh.cols) {
+    const int rows = nrhoSorted[c0 / 2];
+    for (int kc = 0; kc < nkc; ++kc, ++group) {
+      std::vector<Tile>& q = xcdQueue[group % kNumXcd];
+      for (int r0 = 0; r0 < rows; r0 += rowTile) {
+        const int rbN = std::min(sh.rb, (rows - r0 + 31) / 32);
+        q.push_back(Tile{r0, c0, kc * kchunk, kc, rbN, {j1, 0, 0}});
+      }
+    }
+  }
+  size_t longest = 0;
+  for (auto& q : xcdQueue) longest = std::max(longest, q.size());
+  // interleave the per-XCD queues; short queues are padded with no-op
+  // entries (row0 = -1)
+  for (size_t m = 0; m < longest; ++m)
+    for (int x = 0; x < kNumXcd; ++x)
+      out.push_back(m < xcdQueue[x].size() ? xcdQueue[x][m]
+                                           : Tile{-1, 0, 0, 0, 0, {0, 0, 0}});
+}
+
+// Pipeline chunks: consecutive runs of sorted planes with about equal cache
+// bytes each (the resample of chunk c overlaps the screen, contraction and
+// spline of chunk c + 1).
+std::vector<int> make_chunks(const std::vector<int64_t>& bytesSorted, int want) {
+  const int P = (int)bytesSorted.size();
+  int64_t total = 0;
+  for (int64_t b : bytesSorted) total += b;
+  want = std::max(1, std::min(want, P));
+  std::vector<int> cuts{0};
+  int64_t acc = 0;
+  for (int j = 0; j < P; ++j) {
+    acc += bytesSorted[j];
+    const int made = (int)cuts.size();
+    if (made < want && acc * want >= total * made && j + 1 < P) cuts.push_back(j + 1);
+  }
+  cuts.push_back(P);
+  return cuts;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -200,6 +320,53 @@ wkern_status wkern_layout(wkern_plan_t plan, int64_t* offsets, int32_t* nrho) {
   if (!offsets) return fail(WKERN_ERR_INVALID_ARG, "offsets is NULL");
   std::copy(plan->offsets.begin(), plan->offsets.end(), offsets);
   if (nrho) std::copy(plan->nrho.begin(), plan->nrho.end(), nrho);
+  return WKERN_OK;
+}
+
+// Pipeline chunks, resample units and contraction tile lists for `want`
+// chunks (rebuilt by wkern_set_chunks).
+static wkern_status build_chunks(wkern_plan_s* pl, int want) {
+  DevPlan& g = pl->dp;
+  const int P = g.P;
+  const std::vector<int32_t>& perm = pl->perm;
+  std::vector<int64_t> bytesSorted(P);
+  for (int j = 0; j < P; ++j) bytesSorted[j] = pl->offsets[perm[j] + 1] - pl->offsets[perm[j]];
+  pl->chunkJ = make_chunks(bytesSorted, want);
+  pl->nChunks = (int)pl->chunkJ.size() - 1;
+
+  // resample units: blocks of at most 65536 elements of one plane (multiples
+  // of 256, so every wave chunk starts 64-aligned), in chunk order
+  const int64_t unitElems = 65536;
+  std::vector<ResampleUnit> units;
+  pl->chunkU.assign(1, 0);
+  for (int c = 0; c < pl->nChunks; ++c) {
+    for (int j = pl->chunkJ[c]; j < pl->chunkJ[c + 1]; ++j) {
+      const int p = perm[j];
+      const int64_t n = pl->offsets[p + 1] - pl->offsets[p];
+      for (int64_t e0 = 0; e0 < n; e0 += unitElems)
+        units.push_back(ResampleUnit{p, (int32_t)e0, (int32_t)std::min(n, e0 + unitElems), 0});
+    }
+    pl->chunkU.push_back((int)units.size());
+  }
+  g.nUnits = (int)units.size();
+  wkern_status s;
+  pl->release(g.units);
+  if ((s = pl->upload(&g.units, units, "units")) != WKERN_OK) return s;
+
+  for (int v = 0; v < kNumVariants; ++v) {
+    std::vector<Tile> tiles;
+    pl->chunkT[v].assign(1, 0);
+    for (int c = 0; c < pl->nChunks; ++c) {
+      build_tiles(v, pl->chunkJ[c], pl->chunkJ[c + 1], pl->nrhoSorted, g.nkc, g.kchunk, tiles);
+      pl->chunkT[v].push_back((int)tiles.size());
+    }
+    pl->release(pl->d_tiles[v]);
+    if ((s = pl->upload(&pl->d_tiles[v], tiles, "tiles")) != WKERN_OK) return s;
+  }
+  for (hipEvent_t e : pl->evChunk) (void)hipEventDestroy(e);
+  pl->evChunk.assign(pl->nChunks, nullptr);
+  for (auto& e : pl->evChunk)
+    WK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
   return WKERN_OK;
 }
 
@@ -254,43 +421,15 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   g.nrhoSortedHost = pl->nrhoSorted.data();
   g.nrhoMax = nrhoSorted[0];
   g.rowsPad = (int)round_up(g.nrhoMax, kRowAlign);
-  g.colsPad = (int)round_up(2 * (int64_t)P, kColAlign);
+  // column blocks of a chunk may run up to 256 columns past its last plane
+  g.colsPad = (int)round_up(2 * (int64_t)P, kColAlign) + 256;
 
   // K-chunks: the longest power-of-two multiple of 256 dividing NrPad, <= 2048
   g.kchunk = kNrAlign;
   while (g.kchunk * 2 <= 2048 && g.NrPad % (g.kchunk * 2) == 0) g.kchunk *= 2;
   g.nkc = g.NrPad / g.kchunk;
 
-  // contraction tiles: 32 rows x 64 columns (32 planes) per wave, staircase
-  // over the sorted planes: a column block needs the rows of its longest line.
-  // Tiles that read the same screen columns over the same K-chunk form a
-  // group; a group is pinned to one XCD (workgroup i runs on XCD i % 8) and
-  // its tiles are dispatched back to back there, so the group's slice of the
-  // screen is read from HBM once and then served by that XCD's L2.
-  std::vector<std::vector<Tile>> xcdQueue(kNumXcd);
-  const int colTile = 64;
-  int group = 0;
-  for (int c0 = 0; c0 < 2 * P; c0 += colTile) {
-    const int rows = nrhoSorted[c0 / 2];
-    for (int kc = 0; kc < g.nkc; ++kc, ++group) {
-      std::vector<Tile>& q = xcdQueue[group % kNumXcd];
-      for (int r0 = 0; r0 < rows; r0 += 32) q.push_back(Tile{r0, c0, kc * g.kchunk, kc});
-    }
-  }
-  std::vector<Tile> tiles;
-  size_t longest = 0;
-  for (auto& q : xcdQueue) longest = std::max(longest, q.size());
-  // interleave the per-XCD queues; a short queue is padded by repeating its
-  // last tile index as a no-op marker (row0 = -1)
-  for (size_t m = 0; m < longest; ++m)
-    for (int x = 0; x < kNumXcd; ++x)
-      tiles.push_back(m < xcdQueue[x].size() ? xcdQueue[x][m] : Tile{-1, 0, 0, 0});
-  g.nTiles = (int)tiles.size();
-
-  // resample units: blocks of at most 65536 elements of one plane (multiples of
-  // 256, so every wave chunk starts 64-aligned)
-  const int64_t unitElems = 65536;
-  std::vector<ResampleUnit> units;
+  // resample table (caller order)
   std::vector<PlaneInfo> planes(P);
   const int os = d->oversampling;
   for (int p = 0; p < P; ++p) {
@@ -303,11 +442,9 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
     pi.h = (S - 1) / 2;
     pi.lim = (os * pi.h) * (os * pi.h);
     pi.invS = 1.0f / (float)S;
-    const int64_t n = (int64_t)os * os * S * S;
-    for (int64_t e0 = 0; e0 < n; e0 += unitElems)
-      units.push_back(ResampleUnit{p, (int32_t)e0, (int32_t)std::min(n, e0 + unitElems), 0});
   }
-  g.nUnits = (int)units.size();
+
+  pl->perm = perm;
 
   // Thomas coefficients of the spline system: c'_0 = 1/2, c'_k = 1/(4 - c'_{k-1})
   std::vector<double> cprime(std::max(g.nrhoMax, 1));
@@ -330,8 +467,6 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
     return s;
   if ((s = pl->upload(&g.cprime, cprime, "spline table")) != WKERN_OK) return s;
   if ((s = pl->upload(&g.planes, planes, "plane table")) != WKERN_OK) return s;
-  if ((s = pl->upload(&g.tiles, tiles, "tiles")) != WKERN_OK) return s;
-  if ((s = pl->upload(&g.units, units, "units")) != WKERN_OK) return s;
 
   const size_t mElems = (size_t)g.rowsPad * g.NrPad;
   if ((s = pl->alloc(&g.M32, mElems, "M32")) != WKERN_OK) return s;
@@ -351,6 +486,46 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
 
   WK_HIP(launch_hankel_matrix(g, nullptr), "HT matrix launch");
   WK_HIP(hipDeviceSynchronize(), "HT matrix");
+
+  // One chunk by default: measured on the batch workload, running the
+  // resample of one chunk beside the contraction of the next slowed both
+  // (the contraction is L2/HBM-bound as well), so the stages run in turn
+  // unless wkern_set_chunks asks otherwise.
+  if ((s = build_chunks(pl, 1)) != WKERN_OK) return s;
+  WK_HIP(hipStreamCreateWithFlags(&pl->sCompute, hipStreamNonBlocking), "hipStreamCreate");
+  WK_HIP(hipStreamCreateWithFlags(&pl->sStore, hipStreamNonBlocking), "hipStreamCreate");
+  WK_HIP(hipEventCreateWithFlags(&pl->evFork, hipEventDisableTiming), "hipEventCreate");
+  WK_HIP(hipEventCreateWithFlags(&pl->evJoinCompute, hipEventDisableTiming), "hipEventCreate");
+  WK_HIP(hipEventCreateWithFlags(&pl->evJoinStore, hipEventDisableTiming), "hipEventCreate");
+
+  // Autotune: time every contraction variant on this plan's own tile lists
+  // (timing does not depend on the screen values) and keep the fastest.
+  {
+    hipEvent_t a, b;
+    WK_HIP(hipEventCreate(&a), "hipEventCreate");
+    WK_HIP(hipEventCreate(&b), "hipEventCreate");
+    float best = 1e30f;
+    for (int v = 0; v < kNumVariants; ++v) {
+      const int nt = pl->chunkT[v].back();
+      float bestV = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        WK_HIP(hipEventRecord(a, pl->sCompute), "hipEventRecord");
+        WK_HIP(launch_contract(g, v, pl->d_tiles[v], nt, pl->sCompute), "autotune launch");
+        WK_HIP(hipEventRecord(b, pl->sCompute), "hipEventRecord");
+        WK_HIP(hipEventSynchronize(b), "hipEventSynchronize");
+        float ms = 0.f;
+        WK_HIP(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+        if (rep > 0) bestV = std::min(bestV, ms);
+      }
+      pl->variantMs[v] = bestV;
+      if (bestV < best) {
+        best = bestV;
+        pl->variant = v;
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
   return WKERN_OK;
 }
 
@@ -383,6 +558,7 @@ wkern_status wkern_plan(const wkern_desc* d, wkern_plan_t* out) {
   return WKERN_OK;
 }
 
+
 static wkern_status check_gen_args(wkern_plan_t plan, const void* taper, const void* w,
                                    const void* out) {
   if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
@@ -392,6 +568,35 @@ static wkern_status check_gen_args(wkern_plan_t plan, const void* taper, const v
   return WKERN_OK;
 }
 
+// Screen, contraction and spline of pipeline chunk c, then its resample.
+static wkern_status enqueue_chunk(wkern_plan_t plan, int c, const float* taper, const double* w,
+                                  void* out, hipStream_t compute, hipStream_t store,
+                                  hipEvent_t handoff) {
+  const DevPlan& g = plan->dp;
+  const int j0 = plan->chunkJ[c], j1 = plan->chunkJ[c + 1];
+  const int v = plan->variant;
+  const int t0 = plan->chunkT[v][c], t1 = plan->chunkT[v][c + 1];
+  StageRecord* r;
+  wkern_status s;
+  if ((s = plan->record_begin(0, compute, &r)) != WKERN_OK) return s;
+  WK_HIP(launch_screen(g, j0, j1, taper, w, compute), "screen launch");
+  if ((s = record_end(r, compute)) != WKERN_OK) return s;
+  if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;
+  WK_HIP(launch_contract(g, v, plan->d_tiles[v] + t0, t1 - t0, compute), "contraction launch");
+  if ((s = record_end(r, compute)) != WKERN_OK) return s;
+  if ((s = plan->record_begin(2, compute, &r)) != WKERN_OK) return s;
+  WK_HIP(launch_spline(g, j0, j1, compute), "spline launch");
+  if ((s = record_end(r, compute)) != WKERN_OK) return s;
+  if (handoff) {
+    WK_HIP(hipEventRecord(handoff, compute), "hipEventRecord");
+    WK_HIP(hipStreamWaitEvent(store, handoff, 0), "hipStreamWaitEvent");
+  }
+  if ((s = plan->record_begin(3, store, &r)) != WKERN_OK) return s;
+  WK_HIP(launch_resample(g, plan->chunkU[c], plan->chunkU[c + 1], out, store),
+         "resample launch");
+  return record_end(r, store);
+}
+
 wkern_status wkern_generate(wkern_plan_t plan, const float* taper, const double* w, void* out,
                             void* stream) {
   clear_error();
@@ -399,25 +604,21 @@ wkern_status wkern_generate(wkern_plan_t plan, const float* taper, const double*
   if (s != WKERN_OK) return s;
   DeviceGuard guard(plan->desc.device);
   hipStream_t st = (hipStream_t)stream;
-  const DevPlan& g = plan->dp;
-  hipEvent_t* ev = nullptr;
-  if (plan->profiling) {
-    if (plan->eventsUsed == plan->events.size()) {
-      std::array<hipEvent_t, 5> set{};
-      for (auto& e : set) WK_HIP(hipEventCreate(&e), "hipEventCreate");
-      plan->events.push_back(set);
-    }
-    ev = plan->events[plan->eventsUsed++].data();
+  if (plan->profiling) ++plan->profiledCalls;
+  if (plan->nChunks == 1) return enqueue_chunk(plan, 0, taper, w, out, st, st, nullptr);
+  // fork: both internal streams start after the caller's prior work
+  WK_HIP(hipEventRecord(plan->evFork, st), "hipEventRecord");
+  WK_HIP(hipStreamWaitEvent(plan->sCompute, plan->evFork, 0), "hipStreamWaitEvent");
+  WK_HIP(hipStreamWaitEvent(plan->sStore, plan->evFork, 0), "hipStreamWaitEvent");
+  for (int c = 0; c < plan->nChunks; ++c) {
+    s = enqueue_chunk(plan, c, taper, w, out, plan->sCompute, plan->sStore, plan->evChunk[c]);
+    if (s != WKERN_OK) return s;
   }
-  if (ev) WK_HIP(hipEventRecord(ev[0], st), "hipEventRecord");
-  WK_HIP(launch_screen(g, taper, w, st), "screen launch");
-  if (ev) WK_HIP(hipEventRecord(ev[1], st), "hipEventRecord");
-  WK_HIP(launch_contract(g, st), "contraction launch");
-  if (ev) WK_HIP(hipEventRecord(ev[2], st), "hipEventRecord");
-  WK_HIP(launch_spline(g, st), "spline launch");
-  if (ev) WK_HIP(hipEventRecord(ev[3], st), "hipEventRecord");
-  WK_HIP(launch_resample(g, out, st), "resample launch");
-  if (ev) WK_HIP(hipEventRecord(ev[4], st), "hipEventRecord");
+  // join: the caller's later work waits for both
+  WK_HIP(hipEventRecord(plan->evJoinCompute, plan->sCompute), "hipEventRecord");
+  WK_HIP(hipEventRecord(plan->evJoinStore, plan->sStore), "hipEventRecord");
+  WK_HIP(hipStreamWaitEvent(st, plan->evJoinCompute, 0), "hipStreamWaitEvent");
+  WK_HIP(hipStreamWaitEvent(st, plan->evJoinStore, 0), "hipStreamWaitEvent");
   return WKERN_OK;
 }
 
@@ -425,7 +626,10 @@ wkern_status wkern_set_profiling(wkern_plan_t plan, int32_t enable) {
   clear_error();
   if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
   plan->profiling = enable != 0;
-  if (enable) plan->eventsUsed = 0;
+  if (enable) {
+    plan->recordsUsed = 0;
+    plan->profiledCalls = 0;
+  }
   return WKERN_OK;
 }
 
@@ -435,17 +639,49 @@ wkern_status wkern_stage_times(wkern_plan_t plan, double* ms, int32_t* calls) {
   if (!ms) return fail(WKERN_ERR_INVALID_ARG, "ms is NULL");
   DeviceGuard guard(plan->desc.device);
   for (int k = 0; k < 4; ++k) ms[k] = 0.0;
-  for (size_t c = 0; c < plan->eventsUsed; ++c) {
-    auto& ev = plan->events[c];
-    WK_HIP(hipEventSynchronize(ev[4]), "hipEventSynchronize");
-    for (int k = 0; k < 4; ++k) {
-      float t = 0.f;
-      WK_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]), "hipEventElapsedTime");
-      ms[k] += t;
-    }
+  for (size_t i = 0; i < plan->recordsUsed; ++i) {
+    const StageRecord& r = plan->records[i];
+    WK_HIP(hipEventSynchronize(r.end), "hipEventSynchronize");
+    float t = 0.f;
+    WK_HIP(hipEventElapsedTime(&t, r.start, r.end), "hipEventElapsedTime");
+    ms[r.stage] += t;
   }
-  if (calls) *calls = (int32_t)plan->eventsUsed;
+  if (calls) *calls = plan->profiledCalls;
   return WKERN_OK;
+}
+
+wkern_status wkern_plan_info(wkern_plan_t plan, int32_t* variant, int32_t* n_variants,
+                            float* variant_ms, int32_t* chunks) {
+  clear_error();
+  if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
+  if (variant) *variant = plan->variant;
+  if (n_variants) *n_variants = kNumVariants;
+  if (variant_ms)
+    for (int v = 0; v < kNumVariants; ++v) variant_ms[v] = plan->variantMs[v];
+  if (chunks) *chunks = plan->nChunks;
+  return WKERN_OK;
+}
+
+wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant) {
+  clear_error();
+  if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
+  if (variant < 0 || variant >= kNumVariants)
+    return fail(WKERN_ERR_INVALID_ARG, "variant %d not in [0, %d)", variant, kNumVariants);
+  plan->variant = variant;
+  return WKERN_OK;
+}
+
+wkern_status wkern_set_chunks(wkern_plan_t plan, int32_t chunks) {
+  clear_error();
+  if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
+  if (chunks < 1) return fail(WKERN_ERR_INVALID_ARG, "chunks %d < 1", chunks);
+  DeviceGuard guard(plan->desc.device);
+  WK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  try {
+    return build_chunks(plan, chunks);
+  } catch (const std::bad_alloc&) {
+    return fail(WKERN_ERR_OUT_OF_MEMORY, "host allocation");
+  }
 }
 
 wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const double* w,
@@ -456,8 +692,10 @@ wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const 
   DeviceGuard guard(plan->desc.device);
   hipStream_t st = (hipStream_t)stream;
   const DevPlan& g = plan->dp;
-  WK_HIP(launch_screen(g, taper, w, st), "screen launch");
-  WK_HIP(launch_contract(g, st), "contraction launch");
+  const int v = plan->variant;
+  WK_HIP(launch_screen(g, 0, g.P, taper, w, st), "screen launch");
+  WK_HIP(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
+         "contraction launch");
   WK_HIP(launch_lines_out(g, plan->d_lineOffCaller, lines, st), "lines launch");
   return WKERN_OK;
 }

@@ -51,7 +51,30 @@ struct Tile {
   int32_t col0;
   int32_t k0;
   int32_t kc;   // index of the K-chunk (partial-sum slot)
+  int32_t rbN;  // 32-row blocks this tile computes
+  int32_t pad[3];  // pad[0]: end (exclusive, sorted) of the planes it may store
 };
+
+// Contraction variants (candidates of the plan-time autotuner).
+enum ContractVariant {
+  kWave32x64 = 0,   // one wave per tile of 32 rows x 64 columns, direct loads
+  kWave32x128 = 1,  // one wave per tile of 32 rows x 128 columns, direct loads
+  kLds128x128 = 2,  // 4 waves, up to 128 rows of M staged in LDS, 128 columns
+  kLds64x256 = 3,   // 4 waves, up to 64 rows of M staged in LDS, 256 columns
+  kNumVariants = 4
+};
+
+// Tile geometry of a variant: rows per tile = 32 * rb, columns per tile.
+struct ContractShape {
+  int rb;
+  int cols;
+  int pad;
+};
+ContractShape contract_shape(int variant);
+
+// Planes of a pipeline chunk start at multiples of this (in sorted order),
+// so no contraction column block straddles two chunks.
+constexpr int kChunkAlign = 128;
 
 struct DevPlan {
   // geometry
@@ -69,8 +92,6 @@ struct DevPlan {
   double* cprime;         // [nrhoMax] Thomas coefficients
   const int32_t* nrhoSortedHost;  // [P] host copy of nrhoSorted
   PlaneInfo* planes;      // [P] caller order
-  Tile* tiles;
-  int nTiles;
   ResampleUnit* units;
   int nUnits;
   // scratch
@@ -81,10 +102,12 @@ struct DevPlan {
 };
 
 hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s);
-hipError_t launch_screen(const DevPlan& p, const float* taper, const double* w, hipStream_t s);
-hipError_t launch_contract(const DevPlan& p, hipStream_t s);
-hipError_t launch_spline(const DevPlan& p, hipStream_t s);
-hipError_t launch_resample(const DevPlan& p, void* out, hipStream_t s);
+hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, const double* w,
+                         hipStream_t s);
+hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int nTiles,
+                           hipStream_t s);
+hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s);
+hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStream_t s);
 hipError_t launch_lines_out(const DevPlan& p, const int32_t* lineOffCaller, void* lines,
                             hipStream_t s);
 

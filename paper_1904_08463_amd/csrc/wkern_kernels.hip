@@ -85,12 +85,12 @@ __device__ __forceinline__ float2 screen_value(double wv, double ph, float tau) 
 }
 
 // FP32 screen: B32[2j + c][i], sorted plane j, c = 0 (re) / 1 (im).
-__global__ void k_screen_f32(int P, int Nr, int NrPad, const int32_t* __restrict__ perm,
+__global__ void k_screen_f32(int j0, int j1, int Nr, int NrPad, const int32_t* __restrict__ perm,
                              const double* __restrict__ phi, const float* __restrict__ taper,
                              const double* __restrict__ w, float* __restrict__ B32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NrPad) return;
-  for (int j = blockIdx.y; j < P; j += gridDim.y) {
+  for (int j = j0 + blockIdx.y; j < j1; j += gridDim.y) {
     const double wv = w[perm[j]];
     float2 v = make_float2(0.f, 0.f);
     if (i < Nr) v = screen_value(wv, phi[i], taper[i]);
@@ -100,13 +100,14 @@ __global__ void k_screen_f32(int P, int Nr, int NrPad, const int32_t* __restrict
 }
 
 // Split-BF16 screen: Bsplit[col][i/8][term][i%8]; one thread per 8 nodes.
-__global__ void k_screen_bf16(int P, int Nr, int NrPad, const int32_t* __restrict__ perm,
-                              const double* __restrict__ phi, const float* __restrict__ taper,
-                              const double* __restrict__ w, uint16_t* __restrict__ Bsplit) {
+__global__ void k_screen_bf16(int j0, int j1, int Nr, int NrPad,
+                              const int32_t* __restrict__ perm, const double* __restrict__ phi,
+                              const float* __restrict__ taper, const double* __restrict__ w,
+                              uint16_t* __restrict__ Bsplit) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;  // group of 8 nodes
   const int ng = NrPad / 8;
   if (g >= ng) return;
-  for (int j = blockIdx.y; j < P; j += gridDim.y) {
+  for (int j = j0 + blockIdx.y; j < j1; j += gridDim.y) {
     const double wv = w[perm[j]];
     uint16_t re[3][8], im[3][8];
 #pragma unroll
@@ -171,7 +172,7 @@ __device__ __forceinline__ void store_tile(const Tile& t, const double (*accd)[1
     const int col = t.col0 + 32 * cb + rr;
     const int j = col >> 1;
     const int comp = col & 1;
-    if (j >= P) continue;
+    if (j >= P || j >= t.pad[0]) continue;  // pad[0]: end of the tile's chunk
     const int nr = nrhoSorted[j];
     double* dst = part + ((size_t)t.kc * lineTotal + lineOffSorted[j]) * 2 + comp;
 #pragma unroll
@@ -293,6 +294,296 @@ __global__ __launch_bounds__(64) void k_contract_bf16x6(
       for (int r = 0; r < 16; ++r) accd[cb][r] += (double)hi[cb][r] + (double)lo[cb][r];
   }
   store_tile<CB>(t, accd, P, lineTotal, nrhoSorted, lineOffSorted, part);
+}
+
+// --------------------------------------------------------------------------
+// Hankel contraction, LDS-staged version.  A workgroup of 4 waves owns a tile
+// of 32*rbN rows (rbN <= RB) x 128*CB columns.  The rows of M for the
+// current K-block (32 radial nodes) are staged in LDS, double buffered, and
+// shared by the 4 waves; each wave streams its own 32*CB screen columns from
+// global memory into registers, one K-step ahead.  Per K-step of 16 nodes a
+// wave issues 6 * rbN * CB (split) or 8 * rbN * CB (FP32) MFMAs.  Every
+// kSubChunk nodes the FP32 matrix-core sums are added to FP64 running sums.
+// --------------------------------------------------------------------------
+constexpr int kKB = 32;  // radial nodes per LDS stage
+
+template <int RB, int CB>
+__device__ __forceinline__ void store_tile_v2(const Tile& t, int wave, const double (*accd)[16],
+                                              int P, int lineTotal,
+                                              const int32_t* __restrict__ nrhoSorted,
+                                              const int32_t* __restrict__ lineOffSorted,
+                                              double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int col = t.col0 + 32 * (CB * wave + cb) + rr;
+    const int j = col >> 1;
+    const int comp = col & 1;
+    if (j >= P || j >= t.pad[0]) continue;  // pad[0]: end of the tile's chunk
+    const int nr = nrhoSorted[j];
+    double* dst = part + ((size_t)t.kc * lineTotal + lineOffSorted[j]) * 2 + comp;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      if (rb >= t.rbN) break;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = t.row0 + 32 * rb + 8 * (r >> 2) + 4 * hb + (r & 3);
+        if (row < nr) dst[(size_t)row * 2] = accd[rb * CB + cb][r];
+      }
+    }
+  }
+}
+
+template <int RB, int CB>
+__global__ __launch_bounds__(256) void k_contract_bf16x6_lds(
+    const Tile* __restrict__ tiles, int NrPad, int kchunk, int P, int lineTotal,
+    const uint4* __restrict__ Msplit, const uint4* __restrict__ Bsplit,
+    const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
+    double* __restrict__ part) {
+  constexpr int BM = 32 * RB;
+  constexpr int KG = kKB / 8;                 // 8-node groups per stage
+  constexpr int NFILL = BM * KG * 3;          // uint4 per stage
+  constexpr int FILL = (NFILL + 255) / 256;   // per thread
+  __shared__ uint4 lds[2][KG][BM][3];
+  const Tile t = tiles[blockIdx.x];
+  if (t.row0 < 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+  const int ng = NrPad / 8;
+  const int rowsN = 32 * t.rbN;
+
+  // global -> LDS fill assignment: uint4 f = tid + 256 i -> (row, group, term)
+  const uint4* fsrc[FILL];
+  int fdst[FILL];
+  bool fon[FILL];
+#pragma unroll
+  for (int i = 0; i < FILL; ++i) {
+    const int f = tid + 256 * i;
+    const int row = f / (KG * 3);
+    const int c = f - row * (KG * 3);
+    const int kg = c / 3;
+    const int term = c - kg * 3;
+    fon[i] = f < NFILL && row < rowsN;
+    fsrc[i] = Msplit + ((size_t)(t.row0 + (fon[i] ? row : 0)) * ng + kg) * 3 + term;
+    fdst[i] = (kg * BM + row) * 3 + term;
+  }
+  const uint4* bsrc[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+    bsrc[cb] = Bsplit + ((size_t)(t.col0 + 32 * (CB * wave + cb) + rr) * ng + hb) * 3;
+
+  double accd[RB * CB][16];
+#pragma unroll
+  for (int b = 0; b < RB * CB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accd[b][r] = 0.0;
+  f32x16 hi[RB * CB], lo[RB * CB];
+#pragma unroll
+  for (int b = 0; b < RB * CB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      hi[b][r] = 0.f;
+      lo[b][r] = 0.f;
+    }
+
+  const int kEnd = t.k0 + kchunk;
+  uint4 stage[FILL];
+  // prologue: stage 0 into buffer 0
+#pragma unroll
+  for (int i = 0; i < FILL; ++i)
+    if (fon[i]) stage[i] = fsrc[i][(size_t)(t.k0 / 8) * 3];
+#pragma unroll
+  for (int i = 0; i < FILL; ++i)
+    if (fon[i]) (&lds[0][0][0][0])[fdst[i]] = stage[i];
+  uint4 bq[CB][3];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) bq[cb][q] = bsrc[cb][(size_t)(t.k0 / 8) * 3 + q];
+  __syncthreads();
+
+  int buf = 0;
+  for (int kb = t.k0; kb < kEnd; kb += kKB) {
+    const bool more = kb + kKB < kEnd;
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < FILL; ++i)
+        if (fon[i]) stage[i] = fsrc[i][(size_t)((kb + kKB) / 8) * 3];
+    }
+#pragma unroll
+    for (int s = 0; s < kKB / 16; ++s) {
+      const int k = kb + 16 * s;
+      // prefetch the next K-step's screen fragments
+      uint4 bn[CB][3];
+      const bool nextOk = k + 16 < kEnd;
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          bn[cb][q] = nextOk ? bsrc[cb][(size_t)((k + 16) / 8) * 3 + q] : bq[cb][q];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb >= t.rbN) break;
+        const uint4* ap = &lds[buf][2 * s + hb][32 * rb + rr][0];
+        const bf16x8 a0 = as_bf16x8(ap[0]);
+        const bf16x8 a1 = as_bf16x8(ap[1]);
+        const bf16x8 a2 = as_bf16x8(ap[2]);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const int b = rb * CB + cb;
+          const bf16x8 b0 = as_bf16x8(bq[cb][0]);
+          const bf16x8 b1 = as_bf16x8(bq[cb][1]);
+          const bf16x8 b2 = as_bf16x8(bq[cb][2]);
+          lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b2, lo[b], 0, 0, 0);
+          lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, lo[b], 0, 0, 0);
+          lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b0, lo[b], 0, 0, 0);
+          lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, lo[b], 0, 0, 0);
+          lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, lo[b], 0, 0, 0);
+          hi[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, hi[b], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) bq[cb][q] = bn[cb][q];
+    }
+    if (((kb + kKB - t.k0) % kSubChunk) == 0) {
+#pragma unroll
+      for (int b = 0; b < RB * CB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          accd[b][r] += (double)hi[b][r] + (double)lo[b][r];
+          hi[b][r] = 0.f;
+          lo[b][r] = 0.f;
+        }
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < FILL; ++i)
+        if (fon[i]) (&lds[buf ^ 1][0][0][0])[fdst[i]] = stage[i];
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  store_tile_v2<RB, CB>(t, wave, accd, P, lineTotal, nrhoSorted, lineOffSorted, part);
+}
+
+template <int RB, int CB>
+__global__ __launch_bounds__(256) void k_contract_f32_lds(
+    const Tile* __restrict__ tiles, int NrPad, int kchunk, int P, int lineTotal,
+    const float4* __restrict__ M32, const float4* __restrict__ B32,
+    const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
+    double* __restrict__ part) {
+  constexpr int BM = 32 * RB;
+  constexpr int KQ = kKB / 4;              // 4-node quads per stage
+  constexpr int NFILL = BM * KQ;           // float4 per stage
+  constexpr int FILL = (NFILL + 255) / 256;
+  __shared__ float4 lds[2][KQ][BM];
+  const Tile t = tiles[blockIdx.x];
+  if (t.row0 < 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+  const int nq = NrPad / 4;
+  const int rowsN = 32 * t.rbN;
+
+  const float4* fsrc[FILL];
+  int fdst[FILL];
+  bool fon[FILL];
+#pragma unroll
+  for (int i = 0; i < FILL; ++i) {
+    const int f = tid + 256 * i;
+    const int row = f / KQ;
+    const int kq = f - row * KQ;
+    fon[i] = f < NFILL && row < rowsN;
+    fsrc[i] = M32 + (size_t)(t.row0 + (fon[i] ? row : 0)) * nq + kq;
+    fdst[i] = kq * BM + row;
+  }
+  const float4* bsrc[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+    bsrc[cb] = B32 + (size_t)(t.col0 + 32 * (CB * wave + cb) + rr) * nq + hb;
+
+  double accd[RB * CB][16];
+#pragma unroll
+  for (int b = 0; b < RB * CB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accd[b][r] = 0.0;
+  f32x16 acc[RB * CB];
+#pragma unroll
+  for (int b = 0; b < RB * CB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
+
+  const int kEnd = t.k0 + kchunk;
+  float4 stage[FILL];
+#pragma unroll
+  for (int i = 0; i < FILL; ++i)
+    if (fon[i]) stage[i] = fsrc[i][t.k0 / 4];
+#pragma unroll
+  for (int i = 0; i < FILL; ++i)
+    if (fon[i]) (&lds[0][0][0])[fdst[i]] = stage[i];
+  float4 bq[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) bq[cb] = bsrc[cb][t.k0 / 4];
+  __syncthreads();
+
+  int buf = 0;
+  for (int kb = t.k0; kb < kEnd; kb += kKB) {
+    const bool more = kb + kKB < kEnd;
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < FILL; ++i)
+        if (fon[i]) stage[i] = fsrc[i][(kb + kKB) / 4];
+    }
+#pragma unroll
+    for (int s = 0; s < kKB / 8; ++s) {
+      const int k = kb + 8 * s;
+      float4 bn[CB];
+      const bool nextOk = k + 8 < kEnd;
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) bn[cb] = nextOk ? bsrc[cb][(k + 8) / 4] : bq[cb];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb >= t.rbN) break;
+        const float4 a4 = lds[buf][2 * s + hb][32 * rb + rr];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const int b = rb * CB + cb;
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bq[cb].x, acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bq[cb].y, acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bq[cb].z, acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bq[cb].w, acc[b], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) bq[cb] = bn[cb];
+    }
+    if (((kb + kKB - t.k0) % kSubChunk) == 0) {
+#pragma unroll
+      for (int b = 0; b < RB * CB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          accd[b][r] += (double)acc[b][r];
+          acc[b][r] = 0.f;
+        }
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < FILL; ++i)
+        if (fon[i]) (&lds[buf ^ 1][0][0])[fdst[i]] = stage[i];
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  store_tile_v2<RB, CB>(t, wave, accd, P, lineTotal, nrhoSorted, lineOffSorted, part);
 }
 
 // --------------------------------------------------------------------------
@@ -571,46 +862,98 @@ hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_screen(const DevPlan& p, const float* taper, const double* w, hipStream_t s) {
-  const int gy = p.P < 65535 ? p.P : 65535;
+hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, const double* w,
+                         hipStream_t s) {
+  if (j1 <= j0) return hipSuccess;
+  const int gy = (j1 - j0) < 65535 ? (j1 - j0) : 65535;
   if (p.precision == 0) {
     dim3 grid((p.NrPad + 255) / 256, gy);
-    hipLaunchKernelGGL(k_screen_f32, grid, dim3(256), 0, s, p.P, p.Nr, p.NrPad, p.perm, p.phi,
+    hipLaunchKernelGGL(k_screen_f32, grid, dim3(256), 0, s, j0, j1, p.Nr, p.NrPad, p.perm, p.phi,
                        taper, w, p.B32);
   } else {
     dim3 grid((p.NrPad / 8 + 255) / 256, gy);
-    hipLaunchKernelGGL(k_screen_bf16, grid, dim3(256), 0, s, p.P, p.Nr, p.NrPad, p.perm, p.phi,
-                       taper, w, p.Bsplit);
+    hipLaunchKernelGGL(k_screen_bf16, grid, dim3(256), 0, s, j0, j1, p.Nr, p.NrPad, p.perm,
+                       p.phi, taper, w, p.Bsplit);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_contract(const DevPlan& p, hipStream_t s) {
-  if (p.nTiles == 0) return hipSuccess;
+ContractShape contract_shape(int variant) {
+  switch (variant) {
+    case kWave32x64: return ContractShape{1, 64, 1};
+    case kWave32x128: return ContractShape{1, 128, 1};
+    case kLds128x128: return ContractShape{4, 128, 1};
+    default: return ContractShape{2, 256, 1};  // kLds64x256
+  }
+}
+
+hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int nTiles,
+                           hipStream_t s) {
+  if (nTiles <= 0) return hipSuccess;
+  const dim3 g(nTiles);
   if (p.precision == 0) {
-    hipLaunchKernelGGL(k_contract_f32<2>, dim3(p.nTiles), dim3(64), 0, s, p.tiles, p.NrPad,
-                       p.kchunk, p.P, p.lineTotal, p.M32, p.B32, p.nrhoSorted, p.lineOffSorted,
-                       p.part);
+    const float4* A = (const float4*)p.M32;
+    const float4* B = (const float4*)p.B32;
+    switch (variant) {
+      case kWave32x64:
+        hipLaunchKernelGGL(k_contract_f32<2>, g, dim3(64), 0, s, tiles, p.NrPad, p.kchunk, p.P,
+                           p.lineTotal, p.M32, p.B32, p.nrhoSorted, p.lineOffSorted, p.part);
+        break;
+      case kWave32x128:
+        hipLaunchKernelGGL(k_contract_f32<4>, g, dim3(64), 0, s, tiles, p.NrPad, p.kchunk, p.P,
+                           p.lineTotal, p.M32, p.B32, p.nrhoSorted, p.lineOffSorted, p.part);
+        break;
+      case kLds128x128:
+        hipLaunchKernelGGL((k_contract_f32_lds<4, 1>), g, dim3(256), 0, s, tiles, p.NrPad,
+                           p.kchunk, p.P, p.lineTotal, A, B, p.nrhoSorted, p.lineOffSorted,
+                           p.part);
+        break;
+      default:
+        hipLaunchKernelGGL((k_contract_f32_lds<2, 2>), g, dim3(256), 0, s, tiles, p.NrPad,
+                           p.kchunk, p.P, p.lineTotal, A, B, p.nrhoSorted, p.lineOffSorted,
+                           p.part);
+        break;
+    }
   } else {
-    hipLaunchKernelGGL(k_contract_bf16x6<2>, dim3(p.nTiles), dim3(64), 0, s, p.tiles, p.NrPad,
-                       p.kchunk, p.P, p.lineTotal, p.Msplit, p.Bsplit, p.nrhoSorted,
-                       p.lineOffSorted, p.part);
+    const uint4* A = (const uint4*)p.Msplit;
+    const uint4* B = (const uint4*)p.Bsplit;
+    switch (variant) {
+      case kWave32x64:
+        hipLaunchKernelGGL(k_contract_bf16x6<2>, g, dim3(64), 0, s, tiles, p.NrPad, p.kchunk,
+                           p.P, p.lineTotal, p.Msplit, p.Bsplit, p.nrhoSorted, p.lineOffSorted,
+                           p.part);
+        break;
+      case kWave32x128:
+        hipLaunchKernelGGL(k_contract_bf16x6<4>, g, dim3(64), 0, s, tiles, p.NrPad, p.kchunk,
+                           p.P, p.lineTotal, p.Msplit, p.Bsplit, p.nrhoSorted, p.lineOffSorted,
+                           p.part);
+        break;
+      case kLds128x128:
+        hipLaunchKernelGGL((k_contract_bf16x6_lds<4, 1>), g, dim3(256), 0, s, tiles, p.NrPad,
+                           p.kchunk, p.P, p.lineTotal, A, B, p.nrhoSorted, p.lineOffSorted,
+                           p.part);
+        break;
+      default:
+        hipLaunchKernelGGL((k_contract_bf16x6_lds<2, 2>), g, dim3(256), 0, s, tiles, p.NrPad,
+                           p.kchunk, p.P, p.lineTotal, A, B, p.nrhoSorted, p.lineOffSorted,
+                           p.part);
+        break;
+    }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_spline(const DevPlan& p, hipStream_t s) {
+hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s) {
   // Planes are sorted by radial length (longest first); each launch covers a
   // run of planes whose lines fit its LDS size, so short lines are not
   // limited to the occupancy of the longest one.
   static const int kBucket[] = {kMaxRho, 512, 128, 48};
-  int j0 = 0;
-  for (int b = 0; b < 4 && j0 < p.P; ++b) {
+  for (int b = 0; b < 4 && j0 < j1; ++b) {
     const int cap = kBucket[b];
     const int nextCap = b + 1 < 4 ? kBucket[b + 1] : 0;
-    int j1 = j0;
-    while (j1 < p.P && p.nrhoSortedHost[j1] > nextCap) ++j1;
-    if (j1 == j0) continue;
+    int jb = j0;
+    while (jb < j1 && p.nrhoSortedHost[jb] > nextCap) ++jb;
+    if (jb == j0) continue;
     const int nmax = p.nrhoSortedHost[j0] < cap ? p.nrhoSortedHost[j0] : cap;
     const size_t shm = (size_t)3 * nmax * sizeof(double2);
     if (shm > 65536) {
@@ -618,27 +961,26 @@ hipError_t launch_spline(const DevPlan& p, hipStream_t s) {
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_spline, dim3(j1 - j0), dim3(64), shm, s, j0, p.nkc, p.lineTotal,
+    hipLaunchKernelGGL(k_spline, dim3(jb - j0), dim3(64), shm, s, j0, p.nkc, p.lineTotal,
                        p.interp, p.nrhoSorted, p.lineOffSorted, p.cprime, p.part, p.coef);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    j0 = j1;
+    j0 = jb;
   }
   return hipSuccess;
 }
 
-hipError_t launch_resample(const DevPlan& p, void* out, hipStream_t s) {
-  if (p.nUnits == 0) return hipSuccess;
+hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStream_t s) {
+  if (u1 <= u0) return hipSuccess;
   const size_t shm = (size_t)2 * p.nrhoMax * sizeof(float4);
-  hipLaunchKernelGGL(k_resample, dim3(p.nUnits), dim3(256), shm, s, p.units, p.planes, p.coef,
-                     p.os, 1.0f / (float)p.os, (float)p.q, (float2*)out);
+  hipLaunchKernelGGL(k_resample, dim3(u1 - u0), dim3(256), shm, s, p.units + u0, p.planes,
+                     p.coef, p.os, 1.0f / (float)p.os, (float)p.q, (float2*)out);
   return hipGetLastError();
 }
 
 hipError_t launch_lines_out(const DevPlan& p, const int32_t* lineOffCaller, void* lines,
                             hipStream_t s) {
-  const int gy = p.P;
-  dim3 grid(4, gy);
+  dim3 grid(4, p.P);
   hipLaunchKernelGGL(k_lines_out, grid, dim3(256), 0, s, p.P, p.nkc, p.lineTotal, p.perm,
                      p.nrhoSorted, p.lineOffSorted, lineOffCaller, p.part, (double2*)lines);
   return hipGetLastError();

@@ -32,7 +32,8 @@ STATUS = {
 EXPORTS = (
     "wkern_abi_version", "wkern_layout_desc", "wkern_plan", "wkern_layout",
     "wkern_generate", "wkern_generate_radial", "wkern_grad", "wkern_set_profiling",
-    "wkern_stage_times", "wkern_destroy",
+    "wkern_stage_times", "wkern_plan_info", "wkern_set_variant",
+    "wkern_set_chunks", "wkern_destroy",
     "wkern_strerror", "wkern_last_error",
 )
 
@@ -92,6 +93,12 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.wkern_stage_times.restype = ctypes.c_int
     lib.wkern_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
+    lib.wkern_plan_info.restype = ctypes.c_int
+    lib.wkern_plan_info.argtypes = [vp, i32p, i32p, ctypes.POINTER(ctypes.c_float), i32p]
+    lib.wkern_set_variant.restype = ctypes.c_int
+    lib.wkern_set_variant.argtypes = [vp, ctypes.c_int32]
+    lib.wkern_set_chunks.restype = ctypes.c_int
+    lib.wkern_set_chunks.argtypes = [vp, ctypes.c_int32]
     lib.wkern_destroy.restype = ctypes.c_int
     lib.wkern_destroy.argtypes = [vp]
     lib.wkern_strerror.restype = ctypes.c_char_p
@@ -249,6 +256,25 @@ class Plan:
         calls = ctypes.c_int32()
         _check(load_library().wkern_stage_times(self._h, ms, ctypes.byref(calls)))
         return dict(zip(self.STAGES, list(ms))), calls.value
+
+    VARIANTS = ("wave32x64", "wave32x128", "lds128x128", "lds64x256")
+
+    def info(self):
+        """Autotuner choice, candidate timings (ms) and pipeline chunk count."""
+        lib = load_library()
+        v, n, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms = (ctypes.c_float * 16)()
+        _check(lib.wkern_plan_info(self._h, ctypes.byref(v), ctypes.byref(n), ms, ctypes.byref(c)))
+        return {"variant": self.VARIANTS[v.value],
+                "variant_ms": {self.VARIANTS[i]: float(ms[i]) for i in range(n.value)},
+                "chunks": c.value}
+
+    def set_variant(self, variant):
+        v = self.VARIANTS.index(variant) if isinstance(variant, str) else int(variant)
+        _check(load_library().wkern_set_variant(self._h, v))
+
+    def set_chunks(self, chunks: int):
+        _check(load_library().wkern_set_chunks(self._h, int(chunks)))
 
     def plane_views(self, flat):
         """Per-plane [os, os, S, S] views of a flat cache tensor."""

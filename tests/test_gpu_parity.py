@@ -180,3 +180,43 @@ def test_batch_workload_full_size(precision):
         assert e <= GATE[precision], f"plane {p} S={wl.support[p]} w={wl.w[p]:.1f}: {e:.3e}"
     print(f"batch/{precision}: worst error {worst:.3e} over {len(planes)} planes", flush=True)
     plan.close()
+
+
+VARIANTS = ("wave32x64", "wave32x128", "lds128x128", "lds64x256")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_every_contraction_variant(variant, precision):
+    """Every candidate the autotuner may pick, on ragged random planes and on
+    sampled planes of the paper workload."""
+    for wl, planes in ((W.random_small(5, n_planes=45, n_radial=300, os_=5, max_support=41), None),
+                       (W.paper(), [0, 3, 100, 255])):
+        print(f"case {wl.name} variant={variant} precision={precision}", flush=True)
+        plan = _plan(wl, precision)
+        plan.set_variant(variant)
+        taper, w = _inputs(wl)
+        lines = plan.generate_radial(taper, w).cpu().numpy()
+        flat = plan.generate(taper, w).cpu().numpy()
+        pl = list(range(wl.n_planes)) if planes is None else planes
+        caches, ref_lines = H.generate_workload(wl, planes=pl)
+        _check_lines(plan, lines, wl, pl, ref_lines, GATE[precision], f"{wl.name}/{variant}")
+        _check_cache(plan, flat, wl, pl, caches, GATE[precision], f"{wl.name}/{variant}")
+        plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_pipeline_chunks_bitwise(precision):
+    """Splitting the batch into pipeline chunks (the resample of one chunk
+    overlapping the other stages of the next) changes no bit of the output."""
+    wl = W.paper()
+    plan = _plan(wl, precision)
+    taper, w = _inputs(wl)
+    plan.set_chunks(1)
+    ref = plan.generate(taper, w).cpu().numpy()
+    for chunks in (2, 5, 16):
+        plan.set_chunks(chunks)
+        assert plan.info()["chunks"] == chunks
+        got = plan.generate(taper, w).cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), ref.view(np.uint64)), chunks
+    plan.close()
