@@ -140,7 +140,10 @@ wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const 
  * grad_out:   device complex64 [offsets[P]], dL/dRe + j dL/dIm of each value.
  * grad_taper: device float [Nr] (written), dL/dtau_i.
  * grad_w:     device double [P] (written), dL/dw_p.
- * Asynchronous on `stream`.  Errors: INVALID_ARG, DEVICE. */
+ * Every reduction runs in a fixed order (bit-reproducible).  The plan's
+ * gradient scratch is allocated on the first call.  Asynchronous on
+ * `stream`.  Errors: INVALID_ARG, UNSUPPORTED (oversampling > 32),
+ * OUT_OF_MEMORY, DEVICE. */
 wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
                         const void* grad_out, float* grad_taper, double* grad_w,
                         void* stream);

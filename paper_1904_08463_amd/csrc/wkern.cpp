@@ -156,6 +156,10 @@ struct wkern_plan_s {
   hipEvent_t evFork = nullptr, evJoinCompute = nullptr, evJoinStore = nullptr;
   std::vector<hipEvent_t> evChunk;  // [C] compute of chunk c finished
 
+  // adjoint scratch, allocated on the first wkern_grad call
+  GradScratch grad{};
+  bool gradReady = false;
+
   // stage profiling
   bool profiling = false;
   int profiledCalls = 0;
@@ -706,8 +710,25 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
   wkern_status s = check_gen_args(plan, taper, w, grad_out);
   if (s != WKERN_OK) return s;
   if (!grad_taper || !grad_w) return fail(WKERN_ERR_INVALID_ARG, "gradient output is NULL");
-  (void)stream;
-  return fail(WKERN_ERR_UNSUPPORTED, "gradient not built yet");
+  if (plan->desc.oversampling > 32)
+    return fail(WKERN_ERR_UNSUPPORTED, "gradient needs oversampling <= 32");
+  DeviceGuard guard(plan->desc.device);
+  const DevPlan& g = plan->dp;
+  if (!plan->gradReady) {
+    GradScratch& gs = plan->grad;
+    const size_t lt = (size_t)g.lineTotal;
+    if ((s = plan->alloc(&gs.mom, lt * 4, "adjoint moments")) != WKERN_OK) return s;
+    if ((s = plan->alloc(&gs.gy, lt, "adjoint lines")) != WKERN_OK) return s;
+    if ((s = plan->alloc(&gs.gm, lt, "adjoint lines")) != WKERN_OK) return s;
+    if ((s = plan->alloc(&gs.dp, lt, "adjoint lines")) != WKERN_OK) return s;
+    const size_t pn = (size_t)g.P * g.NrPad;
+    if ((s = plan->alloc(&gs.ure, pn, "adjoint screen")) != WKERN_OK) return s;
+    if ((s = plan->alloc(&gs.wterm, pn, "adjoint screen")) != WKERN_OK) return s;
+    plan->gradReady = true;
+  }
+  WK_HIP(launch_grad(g, plan->grad, taper, w, grad_out, grad_taper, grad_w, (hipStream_t)stream),
+         "gradient launch");
+  return WKERN_OK;
 }
 
 wkern_status wkern_destroy(wkern_plan_t plan) {

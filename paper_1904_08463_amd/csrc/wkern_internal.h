@@ -101,6 +101,19 @@ struct DevPlan {
   float4* coef;           // [lineTotal][2]
 };
 
+// Scratch of the adjoint (allocated on the first gradient call).
+struct GradScratch {
+  double2* mom;   // [lineTotal][4] coefficient moments
+  double2* gy;    // [lineTotal] gradient of the radial lines
+  double2* gm;    // [lineTotal] gradient of the second derivatives / Thomas table
+  double2* dp;    // [lineTotal] Thomas right-hand side / solution
+  double* ure;    // [P][NrPad] Re u
+  double* wterm;  // [P][NrPad] 2 pi phi tau Im u
+};
+
+hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* taper,
+                       const double* w, const void* gout, float* gtau, double* gw,
+                       hipStream_t s);
 hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s);
 hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, const double* w,
                          hipStream_t s);

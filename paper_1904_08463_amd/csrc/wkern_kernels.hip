@@ -714,19 +714,27 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
 // truncation of q s: a value that lands one node early or late only moves
 // u slightly outside [0, 1), where the neighbouring cubic piece agrees.
 // --------------------------------------------------------------------------
+// Interval index k and fraction u of the sample at integer offsets (X, Y):
+// t = q sqrt(X^2 + Y^2) in units of the radial node spacing.
+__device__ __forceinline__ void radial_pos(int d2, float q, int nmax, int& k, float& uu) {
+  const float d2f = (float)d2;
+  const float r = __builtin_amdgcn_rsqf(d2f);
+  const bool nz = d2 > 0;
+  const float sq = nz ? d2f * r : 0.f;
+  const float res = fmaf(-sq, sq, d2f);
+  const float corr = nz ? 0.5f * res * r : 0.f;
+  k = min((int)(q * sq), nmax);
+  uu = fmaf(q, corr, fmaf(q, sq, -(float)k));
+}
+
 __device__ __forceinline__ f32x2 cache_value(int X, int Y, int lim, float q, int nmax,
                                              const float4* __restrict__ sc) {
   const int d2 = X * X + Y * Y;
   f32x2 v = {0.f, 0.f};
   if (d2 <= lim) {
-    const float d2f = (float)d2;
-    const float r = __builtin_amdgcn_rsqf(d2f);
-    const bool nz = d2 > 0;
-    const float sq = nz ? d2f * r : 0.f;
-    const float res = fmaf(-sq, sq, d2f);
-    const float corr = nz ? 0.5f * res * r : 0.f;
-    const int k = min((int)(q * sq), nmax);
-    const float uu = fmaf(q, corr, fmaf(q, sq, -(float)k));
+    int k;
+    float uu;
+    radial_pos(d2, q, nmax, k, uu);
     const float4 cr = sc[2 * k];
     const float4 ci = sc[2 * k + 1];
     v.x = fmaf(uu, fmaf(uu, fmaf(uu, cr.w, cr.z), cr.y), cr.x);
@@ -850,6 +858,285 @@ __global__ void k_lines_out(int P, int nkc, int lineTotal, const int32_t* __rest
     }
     lines[co + k] = make_double2(re, im);
   }
+}
+
+// ==========================================================================
+// Adjoint (gradient of a real loss of the kernel cache).  The paper has no
+// gradient; these kernels apply the transposes of the forward steps in
+// reverse order, in FP64, with every reduction in a fixed order (no atomics),
+// so the result is bit-reproducible.
+// ==========================================================================
+
+// Resample transpose, part 1: for interval k of plane p the moments
+//   g_j[k] = sum over cache samples e with interval(e) = k of u(e)^j G(e),
+// j = 0..3 (the gradients of the power-form coefficients c0..c3).  One
+// thread owns (k, fv, fu) and visits the rows b whose |Y| can reach the
+// interval, and in each row the two runs of a whose radius can; the sample
+// is counted only if the forward's own radial_pos assigns it to k, so this
+// is exactly the transpose of what the forward evaluated.  The os^2 partial
+// moments of an interval are then summed in (fv, fu) order.
+constexpr int kMomThreads = 256;
+
+__global__ __launch_bounds__(kMomThreads) void k_resample_T(
+    const PlaneInfo* __restrict__ planes, int os, float q, const float2* __restrict__ g,
+    double2* __restrict__ mom) {
+  extern __shared__ double2 part4[];  // [KPB][os*os][4]
+  const int p = blockIdx.y;
+  const PlaneInfo pi = planes[p];
+  const int os2 = os * os;
+  const int kpb = (kMomThreads + os2 - 1) / os2 > 0 ? max(1, kMomThreads / os2) : 1;
+  const int k0 = blockIdx.x * kpb;
+  const int n = pi.nrho;
+  if (k0 >= n) return;
+  const int nmax = n - 2;
+  const int S = pi.S, h = pi.h;
+  const float2* gp = g + pi.out_off;
+  const float qinv = 1.0f / q;
+  for (int pair = threadIdx.x; pair < kpb * os2; pair += blockDim.x) {
+    const int kk = pair / os2;
+    const int f = pair - kk * os2;
+    const int k = k0 + kk;
+    double2 m0 = make_double2(0, 0), m1 = m0, m2 = m0, m3 = m0;
+    if (k < n && k <= nmax) {
+      const int fv = f / os;
+      const int fu = f - fv * os;
+      // candidate radii (in uv cells of the oversampled grid): (k-1)/q .. (k+2)/q
+      const float rlo = fmaxf(0.f, (float)(k - 1) * qinv);
+      const float rhi = (float)(k + 2) * qinv;
+      const int Rhi = (int)ceilf(rhi) + 1;
+      const float rlo2 = rlo * rlo;
+      // rows: Y = os (b - h) - fv with |Y| <= Rhi
+      const int bmin = max(0, (int)floorf((float)(fv - Rhi) / os) + h);
+      const int bmax = min(S - 1, (int)ceilf((float)(fv + Rhi) / os) + h);
+      for (int b = bmin; b <= bmax; ++b) {
+        const int Y = os * (b - h) - fv;
+        const float rem_hi = rhi * rhi - (float)(Y * Y);
+        if (rem_hi < 0.f) continue;
+        const int Xhi = (int)ceilf(sqrtf(rem_hi)) + 1;
+        const float rem_lo = rlo2 - (float)(Y * Y);
+        const int Xlo = rem_lo > 0.f ? max(0, (int)floorf(sqrtf(rem_lo)) - 1) : -1;
+        // runs X in [-Xhi, -Xlo] and [Xlo, Xhi] (one run [-Xhi, Xhi] when Xlo < 0)
+        for (int side = 0; side < 2; ++side) {
+          int xa, xb;
+          if (Xlo < 0) {
+            if (side == 1) break;
+            xa = -Xhi;
+            xb = Xhi;
+          } else if (side == 0) {
+            xa = -Xhi;
+            xb = -Xlo;
+          } else {
+            xa = Xlo == 0 ? 1 : Xlo;
+            xb = Xhi;
+          }
+          // a with X = os (a - h) - fu in [xa, xb]
+          int a0 = (xa + fu + os * h + os - 1);
+          a0 = a0 >= 0 ? a0 / os : 0;
+          int a1 = xb + fu + os * h;
+          a1 = a1 >= 0 ? a1 / os : -1;
+          a0 = max(a0, 0);
+          a1 = min(a1, S - 1);
+          for (int a = a0; a <= a1; ++a) {
+            const int X = os * (a - h) - fu;
+            const int d2 = X * X + Y * Y;
+            if (d2 > pi.lim) continue;
+            int kk2;
+            float uu;
+            radial_pos(d2, q, nmax, kk2, uu);
+            if (kk2 != k) continue;
+            const float2 gv = gp[((size_t)(f * S + b)) * S + a];
+            const double u1 = uu, u2 = u1 * u1, u3 = u2 * u1;
+            m0.x += gv.x;
+            m0.y += gv.y;
+            m1.x += u1 * gv.x;
+            m1.y += u1 * gv.y;
+            m2.x += u2 * gv.x;
+            m2.y += u2 * gv.y;
+            m3.x += u3 * gv.x;
+            m3.y += u3 * gv.y;
+          }
+        }
+      }
+    }
+    double2* dst = part4 + (size_t)(kk * os2 + f) * 4;
+    dst[0] = m0;
+    dst[1] = m1;
+    dst[2] = m2;
+    dst[3] = m3;
+  }
+  __syncthreads();
+  for (int kk = threadIdx.x; kk < kpb; kk += blockDim.x) {
+    const int k = k0 + kk;
+    if (k >= n) break;
+    double2 acc[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0),
+                      make_double2(0, 0)};
+    for (int f = 0; f < os2; ++f)
+      for (int j = 0; j < 4; ++j) {
+        const double2 v = part4[(size_t)(kk * os2 + f) * 4 + j];
+        acc[j].x += v.x;
+        acc[j].y += v.y;
+      }
+    for (int j = 0; j < 4; ++j) mom[(size_t)(pi.line_off + k) * 4 + j] = acc[j];
+  }
+}
+
+// Resample transpose, part 2: coefficient moments -> gradient of the radial
+// line.  c0 = y_k, c1 = y_{k+1} - y_k - m_k/3 - m_{k+1}/6, c2 = m_k/2,
+// c3 = (m_{k+1} - m_k)/6 give dL/dy and dL/dm; the second derivatives are
+// m = T^-1 D y, so dL/dy += D^T T^-T dL/dm, with T^T solved by Thomas
+// elimination.  One thread per sorted plane (complex arithmetic, real
+// coefficients).  gy, z and dp are FP64 complex scratch of the line layout.
+__global__ void k_spline_T(int P, int interp, const int32_t* __restrict__ nrhoSorted,
+                           const int32_t* __restrict__ lineOffSorted,
+                           const double2* __restrict__ mom, double2* __restrict__ gy,
+                           double2* __restrict__ gm, double2* __restrict__ dp) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P) return;
+  const int n = nrhoSorted[j];
+  const size_t off = lineOffSorted[j];
+  const double2* M = mom + off * 4;
+  double2* y = gy + off;
+  double2* m = gm + off;
+  double2* d = dp + off;
+  for (int k = 0; k < n; ++k) {
+    y[k] = make_double2(0, 0);
+    m[k] = make_double2(0, 0);
+  }
+  for (int k = 0; k < n; ++k) {
+    const double2 g0 = M[4 * k], g1 = M[4 * k + 1], g2 = M[4 * k + 2], g3 = M[4 * k + 3];
+    if (k == n - 1) {  // the last node's interval is the constant y_{n-1}
+      y[k].x += g0.x;
+      y[k].y += g0.y;
+      continue;
+    }
+    if (interp == 1) {
+      y[k].x += g0.x - g1.x;
+      y[k].y += g0.y - g1.y;
+      y[k + 1].x += g1.x;
+      y[k + 1].y += g1.y;
+      m[k].x += -g1.x / 3.0 + 0.5 * g2.x - g3.x / 6.0;
+      m[k].y += -g1.y / 3.0 + 0.5 * g2.y - g3.y / 6.0;
+      m[k + 1].x += -g1.x / 6.0 + g3.x / 6.0;
+      m[k + 1].y += -g1.y / 6.0 + g3.y / 6.0;
+    } else {
+      y[k].x += g0.x - g1.x;
+      y[k].y += g0.y - g1.y;
+      y[k + 1].x += g1.x;
+      y[k + 1].y += g1.y;
+    }
+  }
+  if (interp != 1) return;
+  // T^T rows: 0: [2, 1]; 1..n-3: [1, 4, 1]; n-2: [1, 4, 0]; n-1: [1, 1]
+  // (T: row 0 [2 1], interior [1 4 1], last row m_{n-1} = 0).
+  double cp = 0.5;  // c'_0
+  d[0] = make_double2(m[0].x * 0.5, m[0].y * 0.5);
+  double cprev = cp;
+  // store c'_k in the real slot of a second pass: recompute on the way back
+  for (int k = 1; k < n; ++k) {
+    const double a = 1.0;
+    const double b = (k == n - 1) ? 1.0 : 4.0;
+    const double c = (k >= n - 2) ? 0.0 : 1.0;
+    const double den = b - a * cprev;
+    d[k].x = (m[k].x - a * d[k - 1].x) / den;
+    d[k].y = (m[k].y - a * d[k - 1].y) / den;
+    cprev = c / den;
+  }
+  // back substitution needs c'_k again: recompute forward coefficients lazily
+  // by storing them in m (no longer needed)
+  cprev = 0.5;
+  m[0] = make_double2(0.5, 0.0);
+  for (int k = 1; k < n; ++k) {
+    const double b = (k == n - 1) ? 1.0 : 4.0;
+    const double c = (k >= n - 2) ? 0.0 : 1.0;
+    const double den = b - cprev;
+    cprev = c / den;
+    m[k] = make_double2(cprev, 0.0);
+  }
+  // z_{n-1} = d'_{n-1}; z_k = d'_k - c'_k z_{k+1}  (z overwrites d)
+  for (int k = n - 2; k >= 0; --k) {
+    d[k].x -= m[k].x * d[k + 1].x;
+    d[k].y -= m[k].x * d[k + 1].y;
+  }
+  // y += D^T z: D rows 0: [-6, 6]; k = 1..n-2: [6, -12, 6]; n-1: 0
+  for (int i = 0; i < n; ++i) {
+    double ax = 0.0, ay = 0.0;
+    if (i >= 1 && i - 1 <= n - 2) {
+      ax += 6.0 * d[i - 1].x;
+      ay += 6.0 * d[i - 1].y;
+    }
+    if (i <= n - 2) {
+      const double dd = i == 0 ? -6.0 : -12.0;
+      ax += dd * d[i].x;
+      ay += dd * d[i].y;
+    }
+    if (i + 1 >= 1 && i + 1 <= n - 2) {
+      ax += 6.0 * d[i + 1].x;
+      ay += 6.0 * d[i + 1].y;
+    }
+    y[i].x += ax;
+    y[i].y += ay;
+  }
+}
+
+// Transposed Hankel contraction and screen backward:
+//   G_s[i] = sum_k M[k, i] gy_j[k],  u = G_s exp(-j theta_i),
+//   ure[j][i] = Re u,  wterm[j][i] = 2 pi phi_i tau_i Im u,
+// theta = 2 pi w phi with the phase reduced modulo 1 in FP64.
+__global__ void k_contract_T(int Nr, int NrPad, const int32_t* __restrict__ perm,
+                             const int32_t* __restrict__ nrhoSorted,
+                             const int32_t* __restrict__ lineOffSorted,
+                             const float* __restrict__ M32, const double* __restrict__ phi,
+                             const float* __restrict__ taper, const double* __restrict__ w,
+                             const double2* __restrict__ gy, double* __restrict__ ure,
+                             double* __restrict__ wterm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= Nr) return;
+  const int n = nrhoSorted[j];
+  const double2* y = gy + lineOffSorted[j];
+  double gr = 0.0, gi = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double mk = (double)M32[(size_t)k * NrPad + i];
+    const double2 v = y[k];
+    gr += mk * v.x;
+    gi += mk * v.y;
+  }
+  double t = w[perm[j]] * phi[i];
+  t -= rint(t);
+  double sn, cs;
+  sincospi(2.0 * t, &sn, &cs);
+  const double ur = gr * cs + gi * sn;
+  const double ui = gi * cs - gr * sn;
+  ure[(size_t)j * NrPad + i] = ur;
+  wterm[(size_t)j * NrPad + i] = kTwoPi * phi[i] * (double)taper[i] * ui;
+}
+
+// dL/dtau_i = sum over planes (sorted order) of Re u.
+__global__ void k_grad_taper(int P, int Nr, int NrPad, const double* __restrict__ ure,
+                             float* __restrict__ gtau) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Nr) return;
+  double acc = 0.0;
+  for (int j = 0; j < P; ++j) acc += ure[(size_t)j * NrPad + i];
+  gtau[i] = (float)acc;
+}
+
+// dL/dw_p = sum_i wterm[j][i]: per-thread strided sums, then a fixed tree.
+__global__ __launch_bounds__(256) void k_grad_w(int Nr, int NrPad,
+                                                const int32_t* __restrict__ perm,
+                                                const double* __restrict__ wterm,
+                                                double* __restrict__ gw) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < Nr; i += 256) acc += wterm[(size_t)j * NrPad + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int stride = 128; stride > 0; stride >>= 1) {
+    if ((int)threadIdx.x < stride) red[threadIdx.x] += red[threadIdx.x + stride];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gw[perm[j]] = red[0];
 }
 
 }  // namespace
@@ -983,6 +1270,36 @@ hipError_t launch_lines_out(const DevPlan& p, const int32_t* lineOffCaller, void
   dim3 grid(4, p.P);
   hipLaunchKernelGGL(k_lines_out, grid, dim3(256), 0, s, p.P, p.nkc, p.lineTotal, p.perm,
                      p.nrhoSorted, p.lineOffSorted, lineOffCaller, p.part, (double2*)lines);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* taper,
+                       const double* w, const void* gout, float* gtau, double* gw,
+                       hipStream_t s) {
+  const int os2 = p.os * p.os;
+  const int kpb = os2 >= kMomThreads ? 1 : kMomThreads / os2;
+  const size_t shm = (size_t)kpb * os2 * 4 * sizeof(double2);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_resample_T,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  dim3 g1((p.nrhoMax + kpb - 1) / kpb, p.P);
+  hipLaunchKernelGGL(k_resample_T, g1, dim3(kMomThreads), shm, s, p.planes, p.os, (float)p.q,
+                     (const float2*)gout, gs.mom);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_spline_T, dim3((p.P + 63) / 64), dim3(64), 0, s, p.P, p.interp,
+                     p.nrhoSorted, p.lineOffSorted, gs.mom, gs.gy, gs.gm, gs.dp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  dim3 g3((p.Nr + 255) / 256, p.P);
+  hipLaunchKernelGGL(k_contract_T, g3, dim3(256), 0, s, p.Nr, p.NrPad, p.perm, p.nrhoSorted,
+                     p.lineOffSorted, p.M32, p.phi, taper, w, gs.gy, gs.ure, gs.wterm);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_taper, dim3((p.Nr + 255) / 256), dim3(256), 0, s, p.P, p.Nr,
+                     p.NrPad, gs.ure, gtau);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_w, dim3(p.P), dim3(256), 0, s, p.Nr, p.NrPad, p.perm, gs.wterm, gw);
   return hipGetLastError();
 }
 
