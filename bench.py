@@ -41,16 +41,21 @@ def _parse():
 
 
 def _time_path(plan, taper, w, out, steps, warmup):
+    """Wall time of `steps` generate calls (captured-graph replays), then a
+    separate pass with per-stage HIP events (kernels launched one by one on
+    the same stream) for the stage split."""
     import torch
     for _ in range(warmup):
         plan.generate(taper, w, out)
     torch.cuda.synchronize()
-    plan.set_profiling(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.generate(taper, w, out)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    plan.set_profiling(True)
+    for _ in range(steps):
+        plan.generate(taper, w, out)
     stages, calls = plan.stage_times()
     plan.set_profiling(False)
     return wall, {k: v / max(calls, 1) for k, v in stages.items()}

@@ -123,8 +123,12 @@ wkern_status wkern_layout(wkern_plan_t plan, int64_t* offsets, int32_t* nrho);
  * taper: device float [Nr], tau at r_i (caller owned, read only).
  * w:     device double [P], w of each plane in wavelengths (read only).
  * out:   device complex64 [offsets[P]] (written completely, zeros included).
+ * The launches of one call are captured once into a HIP graph per
+ * (taper, w, out) pointer set and replayed with a single graph launch on
+ * later calls (see wkern_set_graph); when `stream` is itself being captured
+ * by the caller, or profiling is on, the kernels are launched directly.
  * Asynchronous on `stream`.  Errors: INVALID_ARG (NULL plan or pointer),
- * DEVICE (launch failure). */
+ * DEVICE (launch or capture failure). */
 wkern_status wkern_generate(wkern_plan_t plan, const float* taper, const double* w,
                             void* out, void* stream);
 
@@ -168,6 +172,10 @@ wkern_status wkern_stage_times(wkern_plan_t plan, double* ms, int32_t* calls);
  * Errors: INVALID_ARG. */
 wkern_status wkern_plan_info(wkern_plan_t plan, int32_t* variant, int32_t* n_variants,
                              float* variant_ms, int32_t* chunks);
+
+/* enable != 0 (the default): wkern_generate replays a captured HIP graph;
+ * 0: it launches the kernels one by one.  Errors: INVALID_ARG. */
+wkern_status wkern_set_graph(wkern_plan_t plan, int32_t enable);
 
 /* Override the autotuner's choice of contraction variant (0 <= variant <
  * n_variants).  All variants compute the same sums in the same order per

@@ -151,10 +151,17 @@ struct wkern_plan_s {
   std::vector<int> chunkT[kNumVariants];  // [C + 1] tile boundaries
   int variant = kWave32x64;
   float variantMs[kNumVariants] = {};
-  // internal streams (default priority) and their synchronisation
+  // internal streams (default priority): sCompute is the capture stream of
+  // the generation graph, sStore runs the resamples of a chunked pipeline
   hipStream_t sCompute = nullptr, sStore = nullptr;
-  hipEvent_t evFork = nullptr, evJoinCompute = nullptr, evJoinStore = nullptr;
+  hipEvent_t evFork = nullptr, evJoinStore = nullptr;
   std::vector<hipEvent_t> evChunk;  // [C] compute of chunk c finished
+
+  // captured generation graph, keyed by the caller's pointers
+  bool useGraph = true;
+  hipGraphExec_t graphExec = nullptr;
+  const void* graphKey[3] = {nullptr, nullptr, nullptr};
+  bool graphValid = false;
 
   // adjoint scratch, allocated on the first wkern_grad call
   GradScratch grad{};
@@ -171,9 +178,9 @@ struct wkern_plan_s {
       (void)hipEventDestroy(r.start);
       (void)hipEventDestroy(r.end);
     }
+    if (graphExec) (void)hipGraphExecDestroy(graphExec);
     for (hipEvent_t e : evChunk) (void)hipEventDestroy(e);
     if (evFork) (void)hipEventDestroy(evFork);
-    if (evJoinCompute) (void)hipEventDestroy(evJoinCompute);
     if (evJoinStore) (void)hipEventDestroy(evJoinStore);
     if (sCompute) (void)hipStreamDestroy(sCompute);
     if (sStore) (void)hipStreamDestroy(sStore);
@@ -488,6 +495,7 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   if ((s = pl->alloc(&g.coef, (size_t)g.lineTotal * 2, "spline coefficients")) != WKERN_OK)
     return s;
 
+  WK_HIP(prepare_kernels(g), "kernel attributes");
   WK_HIP(launch_hankel_matrix(g, nullptr), "HT matrix launch");
   WK_HIP(hipDeviceSynchronize(), "HT matrix");
 
@@ -499,7 +507,6 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   WK_HIP(hipStreamCreateWithFlags(&pl->sCompute, hipStreamNonBlocking), "hipStreamCreate");
   WK_HIP(hipStreamCreateWithFlags(&pl->sStore, hipStreamNonBlocking), "hipStreamCreate");
   WK_HIP(hipEventCreateWithFlags(&pl->evFork, hipEventDisableTiming), "hipEventCreate");
-  WK_HIP(hipEventCreateWithFlags(&pl->evJoinCompute, hipEventDisableTiming), "hipEventCreate");
   WK_HIP(hipEventCreateWithFlags(&pl->evJoinStore, hipEventDisableTiming), "hipEventCreate");
 
   // Autotune: time every contraction variant on this plan's own tile lists
@@ -601,6 +608,69 @@ static wkern_status enqueue_chunk(wkern_plan_t plan, int c, const float* taper, 
   return record_end(r, store);
 }
 
+// The whole generation: compute stages on `origin`; with several pipeline
+// chunks the resamples run on the plan's store stream, forked from and
+// joined back into `origin`.
+static wkern_status enqueue_all(wkern_plan_t plan, const float* taper, const double* w,
+                                void* out, hipStream_t origin) {
+  if (plan->nChunks == 1) return enqueue_chunk(plan, 0, taper, w, out, origin, origin, nullptr);
+  WK_HIP(hipEventRecord(plan->evFork, origin), "hipEventRecord");
+  WK_HIP(hipStreamWaitEvent(plan->sStore, plan->evFork, 0), "hipStreamWaitEvent");
+  for (int c = 0; c < plan->nChunks; ++c) {
+    wkern_status s =
+        enqueue_chunk(plan, c, taper, w, out, origin, plan->sStore, plan->evChunk[c]);
+    if (s != WKERN_OK) return s;
+  }
+  WK_HIP(hipEventRecord(plan->evJoinStore, plan->sStore), "hipEventRecord");
+  WK_HIP(hipStreamWaitEvent(origin, plan->evJoinStore, 0), "hipStreamWaitEvent");
+  return WKERN_OK;
+}
+
+// Capture enqueue_all on the plan's own stream into a graph for this pointer
+// set (re-captured, and the executable updated or rebuilt, when the caller
+// passes other buffers).
+static wkern_status capture_graph(wkern_plan_t plan, const float* taper, const double* w,
+                                  void* out) {
+  hipGraph_t graph = nullptr;
+  WK_HIP(hipStreamBeginCapture(plan->sCompute, hipStreamCaptureModeRelaxed),
+         "hipStreamBeginCapture");
+  wkern_status s = enqueue_all(plan, taper, w, out, plan->sCompute);
+  hipError_t e = hipStreamEndCapture(plan->sCompute, &graph);
+  if (s != WKERN_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  bool updated = false;
+  if (plan->graphExec) {
+    hipGraphExecUpdateResult res;
+    hipGraphNode_t bad = nullptr;
+    if (hipGraphExecUpdate(plan->graphExec, graph, &bad, &res) == hipSuccess &&
+        res == hipGraphExecUpdateSuccess)
+      updated = true;
+    else {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(plan->graphExec);
+      plan->graphExec = nullptr;
+    }
+  }
+  if (!updated) {
+    e = hipGraphInstantiate(&plan->graphExec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      plan->graphExec = nullptr;
+      plan->graphValid = false;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+  }
+  (void)hipGraphDestroy(graph);
+  plan->graphKey[0] = taper;
+  plan->graphKey[1] = w;
+  plan->graphKey[2] = out;
+  plan->graphValid = true;
+  return WKERN_OK;
+}
+
 wkern_status wkern_generate(wkern_plan_t plan, const float* taper, const double* w, void* out,
                             void* stream) {
   clear_error();
@@ -608,21 +678,26 @@ wkern_status wkern_generate(wkern_plan_t plan, const float* taper, const double*
   if (s != WKERN_OK) return s;
   DeviceGuard guard(plan->desc.device);
   hipStream_t st = (hipStream_t)stream;
-  if (plan->profiling) ++plan->profiledCalls;
-  if (plan->nChunks == 1) return enqueue_chunk(plan, 0, taper, w, out, st, st, nullptr);
-  // fork: both internal streams start after the caller's prior work
-  WK_HIP(hipEventRecord(plan->evFork, st), "hipEventRecord");
-  WK_HIP(hipStreamWaitEvent(plan->sCompute, plan->evFork, 0), "hipStreamWaitEvent");
-  WK_HIP(hipStreamWaitEvent(plan->sStore, plan->evFork, 0), "hipStreamWaitEvent");
-  for (int c = 0; c < plan->nChunks; ++c) {
-    s = enqueue_chunk(plan, c, taper, w, out, plan->sCompute, plan->sStore, plan->evChunk[c]);
-    if (s != WKERN_OK) return s;
+  if (plan->profiling) {
+    ++plan->profiledCalls;
+    return enqueue_all(plan, taper, w, out, st);
   }
-  // join: the caller's later work waits for both
-  WK_HIP(hipEventRecord(plan->evJoinCompute, plan->sCompute), "hipEventRecord");
-  WK_HIP(hipEventRecord(plan->evJoinStore, plan->sStore), "hipEventRecord");
-  WK_HIP(hipStreamWaitEvent(st, plan->evJoinCompute, 0), "hipStreamWaitEvent");
-  WK_HIP(hipStreamWaitEvent(st, plan->evJoinStore, 0), "hipStreamWaitEvent");
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  WK_HIP(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
+  if (!plan->useGraph || cs != hipStreamCaptureStatusNone)
+    return enqueue_all(plan, taper, w, out, st);  // inside the caller's own capture
+  if (!plan->graphValid || plan->graphKey[0] != taper || plan->graphKey[1] != w ||
+      plan->graphKey[2] != out) {
+    if ((s = capture_graph(plan, taper, w, out)) != WKERN_OK) return s;
+  }
+  WK_HIP(hipGraphLaunch(plan->graphExec, st), "hipGraphLaunch");
+  return WKERN_OK;
+}
+
+wkern_status wkern_set_graph(wkern_plan_t plan, int32_t enable) {
+  clear_error();
+  if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
+  plan->useGraph = enable != 0;
   return WKERN_OK;
 }
 
@@ -672,6 +747,7 @@ wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant) {
   if (variant < 0 || variant >= kNumVariants)
     return fail(WKERN_ERR_INVALID_ARG, "variant %d not in [0, %d)", variant, kNumVariants);
   plan->variant = variant;
+  plan->graphValid = false;
   return WKERN_OK;
 }
 
@@ -681,6 +757,7 @@ wkern_status wkern_set_chunks(wkern_plan_t plan, int32_t chunks) {
   if (chunks < 1) return fail(WKERN_ERR_INVALID_ARG, "chunks %d < 1", chunks);
   DeviceGuard guard(plan->desc.device);
   WK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  plan->graphValid = false;
   try {
     return build_chunks(plan, chunks);
   } catch (const std::bad_alloc&) {

@@ -115,6 +115,7 @@ hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* tap
                        const double* w, const void* gout, float* gtau, double* gw,
                        hipStream_t s);
 hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s);
+hipError_t prepare_kernels(const DevPlan& p);
 hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, const double* w,
                          hipStream_t s);
 hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int nTiles,

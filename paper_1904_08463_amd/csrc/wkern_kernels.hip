@@ -1243,11 +1243,6 @@ hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s) {
     if (jb == j0) continue;
     const int nmax = p.nrhoSortedHost[j0] < cap ? p.nrhoSortedHost[j0] : cap;
     const size_t shm = (size_t)3 * nmax * sizeof(double2);
-    if (shm > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_spline,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      if (e != hipSuccess) return e;
-    }
     hipLaunchKernelGGL(k_spline, dim3(jb - j0), dim3(64), shm, s, j0, p.nkc, p.lineTotal,
                        p.interp, p.nrhoSorted, p.lineOffSorted, p.cprime, p.part, p.coef);
     hipError_t e = hipGetLastError();
@@ -1263,6 +1258,18 @@ hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStrea
   hipLaunchKernelGGL(k_resample, dim3(u1 - u0), dim3(256), shm, s, p.units + u0, p.planes,
                      p.coef, p.os, 1.0f / (float)p.os, (float)p.q, (float2*)out);
   return hipGetLastError();
+}
+
+hipError_t prepare_kernels(const DevPlan& p) {
+  // dynamic LDS above 64 KiB must be enabled per kernel before any launch
+  // (and before any stream capture)
+  const size_t shmSpline = (size_t)3 * p.nrhoMax * sizeof(double2);
+  if (shmSpline > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_spline,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmSpline);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_lines_out(const DevPlan& p, const int32_t* lineOffCaller, void* lines,

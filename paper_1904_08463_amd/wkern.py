@@ -33,7 +33,7 @@ EXPORTS = (
     "wkern_abi_version", "wkern_layout_desc", "wkern_plan", "wkern_layout",
     "wkern_generate", "wkern_generate_radial", "wkern_grad", "wkern_set_profiling",
     "wkern_stage_times", "wkern_plan_info", "wkern_set_variant",
-    "wkern_set_chunks", "wkern_destroy",
+    "wkern_set_chunks", "wkern_set_graph", "wkern_destroy",
     "wkern_strerror", "wkern_last_error",
 )
 
@@ -97,6 +97,8 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_plan_info.argtypes = [vp, i32p, i32p, ctypes.POINTER(ctypes.c_float), i32p]
     lib.wkern_set_variant.restype = ctypes.c_int
     lib.wkern_set_variant.argtypes = [vp, ctypes.c_int32]
+    lib.wkern_set_graph.restype = ctypes.c_int
+    lib.wkern_set_graph.argtypes = [vp, ctypes.c_int32]
     lib.wkern_set_chunks.restype = ctypes.c_int
     lib.wkern_set_chunks.argtypes = [vp, ctypes.c_int32]
     lib.wkern_destroy.restype = ctypes.c_int
@@ -272,6 +274,9 @@ class Plan:
     def set_variant(self, variant):
         v = self.VARIANTS.index(variant) if isinstance(variant, str) else int(variant)
         _check(load_library().wkern_set_variant(self._h, v))
+
+    def set_graph(self, enable: bool):
+        _check(load_library().wkern_set_graph(self._h, 1 if enable else 0))
 
     def set_chunks(self, chunks: int):
         _check(load_library().wkern_set_chunks(self._h, int(chunks)))
