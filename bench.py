@@ -37,6 +37,8 @@ def _parse():
     ap.add_argument("--cpu-stride", type=int, default=16,
                     help="oracle sample: every n-th plane in support order")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--skip-fft", action="store_true")
+    ap.add_argument("--fft-steps", type=int, default=2)
     return ap.parse_args()
 
 
@@ -70,6 +72,40 @@ def _sampled_error(plan, out, wl, planes):
         ref = caches[j].reshape(-1)
         worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
     return worst
+
+
+def _fft_paths(wl, taper, w, out, steps):
+    """The standard algorithm (zero-padded 2D FFT per plane) on the same GPU:
+    the paper's fixed workspace (power of two >= max support) and a per-plane
+    workspace (power of two >= S_p)."""
+    import torch
+    from oracle import fft2d as F
+    from paper_1904_08463_amd import FFT2DPlan
+    res = {}
+    fov = wl.image_size * wl.cellsize
+    tfn = F.taper_from_samples(wl.taper, 0.5 * fov)
+    order = np.argsort(wl.support, kind="stable")
+    check = sorted(set(order[[0, 9000]].tolist()))
+    for mode in ("max_support", "per_plane"):
+        plan = FFT2DPlan.from_workload(wl, workspace=mode)
+        plan.generate(taper, w, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.generate(taper, w, out)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        worst = 0.0
+        for p in check:
+            s = int(wl.support[p])
+            n_ws = F.next_pow2(wl.max_support if mode == "max_support" else s)
+            ref = F.generate(tfn, [wl.w[p]], [s], wl.oversampling, n_ws, fov)[0].reshape(-1)
+            got = out[int(plan.offsets[p]):int(plan.offsets[p + 1])].cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+        plan.close()
+        res[f"fft2d_{mode}"] = {"kernels_per_s": wl.n_planes / wall, "ms_per_step": 1000.0 * wall,
+                                "steps": steps, "max_rel_err_sampled_vs_2d_twin": worst}
+    return res
 
 
 def _cpu_baseline(wl, stride):
@@ -149,6 +185,9 @@ def main():
                          "contraction_variant": info32["variant"],
                          "autotune_ms": info32["variant_ms"]}
         plan32.close()
+
+    if not args.skip_fft:
+        paths.update(_fft_paths(wl, taper, w, out, args.fft_steps))
 
     line = {
         "metric": "w-kernels/sec at <=1e-6 rel err (split-BF16 Hankel; FP32 Hankel beside it)",

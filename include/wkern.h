@@ -198,6 +198,37 @@ const char* wkern_strerror(wkern_status s);
 /* Detail of the last error on the calling thread ("" if none). */
 const char* wkern_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Comparison path: the standard algorithm (section 3, Algorithm 1).  For
+ * each plane the IAA-kernel times the w-kernel on an N x N image-domain
+ * workspace, zero padded by the oversampling factor to L = os N, a 2D FFT
+ * (rocFFT through hipFFT, FP32) and extraction of the kernel cache, with the
+ * same output layout, sample offsets and circular support as wkern_generate.
+ * Workspace undersampling (section 4.2): N is a power of two at or above
+ * the kernel's full width.  The taper samples at r_i are interpolated
+ * linearly in r onto the workspace pixels; pixels outside the open disc
+ * r < r_max are zero.  It is kept beside the Hankel path to be timed
+ * against it; it is not the method this library accelerates.
+ * ------------------------------------------------------------------------- */
+typedef struct wkern_fft2d_s* wkern_fft2d_t;
+
+/* workspace_mode 0: one N for all planes, the power of two at or above
+ * max_support (the setting the paper's imager used, sections 5 and 6.3);
+ * 1: per plane, the power of two at or above S_p.  workspace_bytes: device
+ * memory for batched transforms (<= 0: 2 GiB); planes are transformed in
+ * batches that fit it.  Uses d's geometry, supports and device; precision
+ * and interp are ignored.  Errors: INVALID_ARG, UNSUPPORTED (L > 16384),
+ * DEVICE, OUT_OF_MEMORY. */
+wkern_status wkern_fft2d_plan(const wkern_desc* d, int32_t workspace_mode,
+                              int64_t workspace_bytes, wkern_fft2d_t* out);
+
+/* Same arguments and output as wkern_generate.  Asynchronous on `stream`. */
+wkern_status wkern_fft2d_generate(wkern_fft2d_t plan, const float* taper, const double* w,
+                                  void* out, void* stream);
+
+/* Release the comparison plan (synchronises its device first). */
+wkern_status wkern_fft2d_destroy(wkern_fft2d_t plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,5 +4,5 @@ The compute path is the HIP library ``libwkern.so`` (C ABI in
 ``include/wkern.h``); ``wkern`` is its Python binding and ``autograd`` wraps
 it in a ``torch.autograd.Function``.
 """
-from .wkern import (ABI_VERSION, EXPORTS, Plan, WkernError, layout_desc,  # noqa: F401
-                    load_library)
+from .wkern import (ABI_VERSION, EXPORTS, FFT2DPlan, Plan, WkernError,  # noqa: F401
+                    layout_desc, load_library)

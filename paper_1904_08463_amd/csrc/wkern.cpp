@@ -123,6 +123,8 @@ struct DeviceGuard {
 
 }  // namespace
 
+void wkern::set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
 // One profiled launch: stage index and the events around it.
 struct StageRecord {
   int stage;

@@ -6,6 +6,9 @@
 
 namespace wkern {
 
+// Sets the calling thread's detail string returned by wkern_last_error().
+void set_last_error(const char* msg);
+
 // Radial K-chunk accumulated in FP32 inside the matrix cores before it is
 // added to an FP64 running sum.
 constexpr int kSubChunk = 128;

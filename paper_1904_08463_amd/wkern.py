@@ -35,6 +35,7 @@ EXPORTS = (
     "wkern_stage_times", "wkern_plan_info", "wkern_set_variant",
     "wkern_set_chunks", "wkern_set_graph", "wkern_destroy",
     "wkern_strerror", "wkern_last_error",
+    "wkern_fft2d_plan", "wkern_fft2d_generate", "wkern_fft2d_destroy",
 )
 
 
@@ -107,6 +108,12 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_strerror.argtypes = [ctypes.c_int]
     lib.wkern_last_error.restype = ctypes.c_char_p
     lib.wkern_last_error.argtypes = []
+    lib.wkern_fft2d_plan.restype = ctypes.c_int
+    lib.wkern_fft2d_plan.argtypes = [desc_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(vp)]
+    lib.wkern_fft2d_generate.restype = ctypes.c_int
+    lib.wkern_fft2d_generate.argtypes = [vp, vp, vp, vp, vp]
+    lib.wkern_fft2d_destroy.restype = ctypes.c_int
+    lib.wkern_fft2d_destroy.argtypes = [vp]
     if lib.wkern_abi_version() != ABI_VERSION:
         raise WkernError(5, f"library ABI {lib.wkern_abi_version()}, binding {ABI_VERSION}")
     _lib = lib
@@ -303,3 +310,51 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class FFT2DPlan:
+    """The standard algorithm (2D FFT of the zero-padded workspace) on the GPU,
+    for comparison with Plan; same output layout."""
+
+    WORKSPACE = {"max_support": 0, "per_plane": 1}
+
+    def __init__(self, image_size: int, cellsize: float, n_radial: int, oversampling: int,
+                 support: Sequence[int], max_support: Optional[int] = None,
+                 workspace: str = "max_support", workspace_bytes: int = 0, device: int = 0):
+        lib = load_library()
+        d, sup = make_desc(image_size, cellsize, n_radial, oversampling, support, max_support,
+                           1, "fp32", "cubic", device)
+        h = ctypes.c_void_p()
+        _check(lib.wkern_fft2d_plan(ctypes.byref(d), self.WORKSPACE[workspace],
+                                    int(workspace_bytes), ctypes.byref(h)))
+        self._h = h
+        self.n_planes = int(d.n_planes)
+        self.n_radial = int(n_radial)
+        self.offsets, _ = layout_desc(image_size=image_size, cellsize=cellsize, n_radial=n_radial,
+                                      oversampling=oversampling, support=sup,
+                                      max_support=d.max_support)
+
+    @classmethod
+    def from_workload(cls, wl, workspace: str = "max_support", device: int = 0):
+        return cls(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, wl.support,
+                   wl.max_support, workspace, 0, device)
+
+    def generate(self, taper, w, out=None, stream=None):
+        import torch
+        total = int(self.offsets[-1])
+        if out is None:
+            out = torch.empty(total, dtype=torch.complex64, device=taper.device)
+        _check(load_library().wkern_fft2d_generate(self._h, _ptr(taper), _ptr(w), _ptr(out),
+                                                   _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load_library().wkern_fft2d_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

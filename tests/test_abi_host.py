@@ -26,7 +26,7 @@ def lib():
 def test_header_symbols_exported(lib):
     with open(os.path.join(ROOT, "include", "wkern.h")) as f:
         hdr = f.read()
-    declared = set(re.findall(r"^\S[^\n(]*?\b(wkern_[a-z_]+)\s*\(", hdr, flags=re.M))
+    declared = set(re.findall(r"^\S[^\n(]*?\b(wkern_[a-z_0-9]+)\s*\(", hdr, flags=re.M))
     assert declared == set(lib_mod.EXPORTS)
     for name in declared:
         assert hasattr(lib, name), name
