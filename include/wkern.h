@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define WKERN_ABI_VERSION 1
+#define WKERN_ABI_VERSION 2
 
 typedef enum {
   WKERN_OK = 0,
@@ -95,6 +95,12 @@ typedef struct {
   wkern_precision precision;
   wkern_interp interp;
   int32_t device;          /* HIP device ordinal */
+  /* host [P] or NULL.  Absolute w-term (section 4.1): K(-w) = conj K(w) for
+   * a real taper.  mirror[p] = q >= 0 declares that w[p] = -w[q]; plane p is
+   * then not computed but written as the exact conjugate of plane q, and
+   * w[p] is not read.  q must have mirror[q] = -1 and S_q = S_p.
+   * mirror[p] = -1 (or a NULL table): plane p is computed from w[p]. */
+  const int32_t* mirror;
 } wkern_desc;
 
 /* Version of the ABI this library was built with (== WKERN_ABI_VERSION). */
@@ -143,7 +149,9 @@ wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const 
  * paper has no gradient, this is the chain rule through the steps above).
  * grad_out:   device complex64 [offsets[P]], dL/dRe + j dL/dIm of each value.
  * grad_taper: device float [Nr] (written), dL/dtau_i.
- * grad_w:     device double [P] (written), dL/dw_p.
+ * grad_w:     device double [P] (written), dL/dw_p.  For a mirrored plane p
+ *             (mirror[p] = q) the cache is a function of w[q]: its share of
+ *             the gradient is folded into grad_w[q] and grad_w[p] = 0.
  * Every reduction runs in a fixed order (bit-reproducible).  The plan's
  * gradient scratch is allocated on the first call.  Asynchronous on
  * `stream`.  Errors: INVALID_ARG, UNSUPPORTED (oversampling > 32),

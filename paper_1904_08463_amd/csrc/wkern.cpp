@@ -90,6 +90,19 @@ wkern_status validate(const wkern_desc* d) {
       return fail(WKERN_ERR_INVALID_ARG, "support[%d] = %d must be odd in [1, %d]", p, s,
                   d->max_support);
   }
+  if (d->mirror) {
+    for (int p = 0; p < d->n_planes; ++p) {
+      const int q = d->mirror[p];
+      if (q == -1) continue;
+      if (q < 0 || q >= d->n_planes || q == p)
+        return fail(WKERN_ERR_INVALID_ARG, "mirror[%d] = %d is not -1 or another plane", p, q);
+      if (d->mirror[q] != -1)
+        return fail(WKERN_ERR_INVALID_ARG, "mirror[%d] = %d names a mirrored plane", p, q);
+      if (d->support[q] != d->support[p])
+        return fail(WKERN_ERR_INVALID_ARG, "mirror[%d] = %d: supports %d and %d differ", p, q,
+                    d->support[p], d->support[q]);
+    }
+  }
   return WKERN_OK;
 }
 
@@ -137,11 +150,13 @@ struct wkern_plan_s {
   std::vector<int32_t> support;
   std::vector<int64_t> offsets;       // [P + 1]
   std::vector<int32_t> nrho;          // [P] caller order
-  std::vector<int32_t> lineOffCaller; // [P + 1]
-  std::vector<int32_t> nrhoSorted;    // [P] longest first
+  std::vector<int32_t> lineOffCaller; // [Pall + 1]
+  std::vector<int32_t> mirror;        // [Pall] -1 or the source plane
+  std::vector<int32_t> nrhoSorted;    // [P] computed planes, longest first
   std::vector<int32_t> perm;          // [P] sorted j -> caller p
+  std::vector<int32_t> mirStart;      // [P + 1]
+  std::vector<int32_t> mirList;       // mirrored planes grouped by source
   DevPlan dp{};
-  int32_t* d_lineOffCaller = nullptr;
   std::vector<void*> allocations;
 
   // pipeline chunks over the sorted planes
@@ -342,8 +357,18 @@ static wkern_status build_chunks(wkern_plan_s* pl, int want) {
   DevPlan& g = pl->dp;
   const int P = g.P;
   const std::vector<int32_t>& perm = pl->perm;
+  // planes written by sorted plane j: itself and its mirrors
+  auto written = [&](int j, std::vector<int>& out) {
+    out.assign(1, perm[j]);
+    for (int m = pl->mirStart[j]; m < pl->mirStart[j + 1]; ++m) out.push_back(pl->mirList[m]);
+  };
+  std::vector<int> wr;
   std::vector<int64_t> bytesSorted(P);
-  for (int j = 0; j < P; ++j) bytesSorted[j] = pl->offsets[perm[j] + 1] - pl->offsets[perm[j]];
+  for (int j = 0; j < P; ++j) {
+    written(j, wr);
+    bytesSorted[j] = 0;
+    for (int p : wr) bytesSorted[j] += pl->offsets[p + 1] - pl->offsets[p];
+  }
   pl->chunkJ = make_chunks(bytesSorted, want);
   pl->nChunks = (int)pl->chunkJ.size() - 1;
 
@@ -354,10 +379,12 @@ static wkern_status build_chunks(wkern_plan_s* pl, int want) {
   pl->chunkU.assign(1, 0);
   for (int c = 0; c < pl->nChunks; ++c) {
     for (int j = pl->chunkJ[c]; j < pl->chunkJ[c + 1]; ++j) {
-      const int p = perm[j];
-      const int64_t n = pl->offsets[p + 1] - pl->offsets[p];
-      for (int64_t e0 = 0; e0 < n; e0 += unitElems)
-        units.push_back(ResampleUnit{p, (int32_t)e0, (int32_t)std::min(n, e0 + unitElems), 0});
+      written(j, wr);
+      for (int p : wr) {
+        const int64_t n = pl->offsets[p + 1] - pl->offsets[p];
+        for (int64_t e0 = 0; e0 < n; e0 += unitElems)
+          units.push_back(ResampleUnit{p, (int32_t)e0, (int32_t)std::min(n, e0 + unitElems), 0});
+      }
     }
     pl->chunkU.push_back((int)units.size());
   }
@@ -392,8 +419,12 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   pl->nrho.resize(P);
   layout_host(&pl->desc, pl->offsets.data(), pl->nrho.data());
 
+  pl->mirror.assign(P, -1);
+  if (d->mirror) pl->mirror.assign(d->mirror, d->mirror + P);
+  pl->desc.mirror = pl->mirror.data();
+
   DevPlan& g = pl->dp;
-  g.P = P;
+  g.Pall = P;
   g.Nr = d->n_radial;
   g.NrPad = (int)round_up(d->n_radial, kNrAlign);
   g.os = d->oversampling;
@@ -406,22 +437,37 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   g.dr = r_max / d->n_radial;
   g.drho = du / ((double)d->radial_refine * d->oversampling);
 
-  // planes sorted by radial length, longest first (ties: caller order)
-  std::vector<int32_t> perm(P);
-  for (int p = 0; p < P; ++p) perm[p] = p;
+  // computed planes (not mirrored), sorted by radial length, longest first
+  // (ties: caller order)
+  std::vector<int32_t> perm;
+  for (int p = 0; p < P; ++p)
+    if (pl->mirror[p] < 0) perm.push_back(p);
   std::stable_sort(perm.begin(), perm.end(),
                    [&](int a, int b) { return pl->nrho[a] > pl->nrho[b]; });
-  std::vector<int32_t> nrhoSorted(P), lineOffSorted(P + 1);
+  const int Pc = (int)perm.size();
+  g.P = Pc;
+  std::vector<int32_t> nrhoSorted(Pc), lineOffSorted(Pc + 1);
   int64_t acc = 0;
-  for (int j = 0; j < P; ++j) {
+  for (int j = 0; j < Pc; ++j) {
     nrhoSorted[j] = pl->nrho[perm[j]];
     lineOffSorted[j] = (int32_t)acc;
     acc += nrhoSorted[j];
   }
-  lineOffSorted[P] = (int32_t)acc;
+  lineOffSorted[Pc] = (int32_t)acc;
   g.lineTotal = (int)acc;
-  std::vector<int32_t> sortedPos(P);
-  for (int j = 0; j < P; ++j) sortedPos[perm[j]] = j;
+  std::vector<int32_t> sortedPos(P, -1);
+  for (int j = 0; j < Pc; ++j) sortedPos[perm[j]] = j;
+  // mirrored planes grouped by their source (sorted order)
+  pl->mirStart.assign(Pc + 1, 0);
+  for (int p = 0; p < P; ++p)
+    if (pl->mirror[p] >= 0) ++pl->mirStart[sortedPos[pl->mirror[p]] + 1];
+  for (int j = 0; j < Pc; ++j) pl->mirStart[j + 1] += pl->mirStart[j];
+  pl->mirList.assign(pl->mirStart[Pc], 0);
+  {
+    std::vector<int32_t> fillPos(pl->mirStart.begin(), pl->mirStart.end() - 1);
+    for (int p = 0; p < P; ++p)
+      if (pl->mirror[p] >= 0) pl->mirList[fillPos[sortedPos[pl->mirror[p]]]++] = p;
+  }
   pl->lineOffCaller.resize(P + 1);
   acc = 0;
   for (int p = 0; p < P; ++p) {
@@ -429,13 +475,14 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
     acc += pl->nrho[p];
   }
   pl->lineOffCaller[P] = (int32_t)acc;
+  g.lineTotalAll = (int)acc;
 
   pl->nrhoSorted = nrhoSorted;
   g.nrhoSortedHost = pl->nrhoSorted.data();
   g.nrhoMax = nrhoSorted[0];
   g.rowsPad = (int)round_up(g.nrhoMax, kRowAlign);
   // column blocks of a chunk may run up to 256 columns past its last plane
-  g.colsPad = (int)round_up(2 * (int64_t)P, kColAlign) + 256;
+  g.colsPad = (int)round_up(2 * (int64_t)Pc, kColAlign) + 256;
 
   // K-chunks: the longest power-of-two multiple of 256 dividing NrPad, <= 2048
   g.kchunk = kNrAlign;
@@ -448,8 +495,11 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   for (int p = 0; p < P; ++p) {
     const int S = d->support[p];
     PlaneInfo& pi = planes[p];
+    const int src = pl->mirror[p] >= 0 ? pl->mirror[p] : p;
     pi.out_off = pl->offsets[p];
-    pi.line_off = lineOffSorted[sortedPos[p]];
+    pi.line_off = lineOffSorted[sortedPos[src]];
+    pi.conj = pl->mirror[p] >= 0 ? 1 : 0;
+    pi.line_off_caller = pl->lineOffCaller[p];
     pi.nrho = pl->nrho[p];
     pi.S = S;
     pi.h = (S - 1) / 2;
@@ -476,8 +526,10 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   if ((s = pl->upload(&g.perm, perm, "perm")) != WKERN_OK) return s;
   if ((s = pl->upload(&g.nrhoSorted, nrhoSorted, "nrho")) != WKERN_OK) return s;
   if ((s = pl->upload(&g.lineOffSorted, lineOffSorted, "line offsets")) != WKERN_OK) return s;
-  if ((s = pl->upload(&pl->d_lineOffCaller, pl->lineOffCaller, "line offsets")) != WKERN_OK)
+  if ((s = pl->upload(&g.lineOffCaller, pl->lineOffCaller, "line offsets")) != WKERN_OK)
     return s;
+  if ((s = pl->upload(&g.mirStart, pl->mirStart, "mirror table")) != WKERN_OK) return s;
+  if ((s = pl->upload(&g.mirList, pl->mirList, "mirror table")) != WKERN_OK) return s;
   if ((s = pl->upload(&g.cprime, cprime, "spline table")) != WKERN_OK) return s;
   if ((s = pl->upload(&g.planes, planes, "plane table")) != WKERN_OK) return s;
 
@@ -779,7 +831,7 @@ wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const 
   WK_HIP(launch_screen(g, 0, g.P, taper, w, st), "screen launch");
   WK_HIP(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
          "contraction launch");
-  WK_HIP(launch_lines_out(g, plan->d_lineOffCaller, lines, st), "lines launch");
+  WK_HIP(launch_lines_out(g, lines, st), "lines launch");
   return WKERN_OK;
 }
 
@@ -796,7 +848,8 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
   if (!plan->gradReady) {
     GradScratch& gs = plan->grad;
     const size_t lt = (size_t)g.lineTotal;
-    if ((s = plan->alloc(&gs.mom, lt * 4, "adjoint moments")) != WKERN_OK) return s;
+    if ((s = plan->alloc(&gs.mom, (size_t)g.lineTotalAll * 4, "adjoint moments")) != WKERN_OK)
+      return s;
     if ((s = plan->alloc(&gs.gy, lt, "adjoint lines")) != WKERN_OK) return s;
     if ((s = plan->alloc(&gs.gm, lt, "adjoint lines")) != WKERN_OK) return s;
     if ((s = plan->alloc(&gs.dp, lt, "adjoint lines")) != WKERN_OK) return s;

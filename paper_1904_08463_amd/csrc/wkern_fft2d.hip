@@ -52,7 +52,7 @@ struct FftPlane {
   int32_t S;
   int32_t h;
   int32_t lim;
-  int32_t pad;
+  int32_t pad;  // os^2 S^2, the plane's element count
 };
 
 // Workspace of one batch: sample (kx, ky) of the L x L transform input holds
@@ -140,6 +140,21 @@ __global__ void k_fft_extract(int os, int L, int g0, const int32_t* __restrict__
   }
 }
 
+// Mirrored planes (section 4.1): the cache of plane p is the conjugate of
+// its source plane's.
+__global__ void k_conj_copy(int nm, const int32_t* __restrict__ mir, const int32_t* __restrict__ src,
+                            const FftPlane* __restrict__ info, float2* __restrict__ out) {
+  const int m = blockIdx.y;
+  if (m >= nm) return;
+  const FftPlane pd = info[mir[m]];
+  const FftPlane ps = info[src[m]];
+  const int n = (int)(pd.pad);  // element count of the plane
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const float2 v = out[ps.out_off + e];
+    out[pd.out_off + e] = make_float2(v.x, -v.y);
+  }
+}
+
 int next_pow2(int n) {
   int p = 1;
   while (p < n) p <<= 1;
@@ -162,7 +177,11 @@ struct FftGroup {
 struct wkern_fft2d_s {
   wkern_desc desc{};
   std::vector<int32_t> support;
+  std::vector<int32_t> mirror;
   std::vector<int64_t> offsets;
+  int nMirror = 0;
+  int32_t* dMir = nullptr;     // mirrored planes
+  int32_t* dMirSrc = nullptr;  // their sources
   double dl0 = 0.0;  // FOV, divided by N per group
   double dr = 0.0;
   std::vector<FftGroup> groups;
@@ -178,6 +197,8 @@ struct wkern_fft2d_s {
     if (work) (void)hipFree(work);
     if (dPlanes) (void)hipFree(dPlanes);
     if (dInfo) (void)hipFree(dInfo);
+    if (dMir) (void)hipFree(dMir);
+    if (dMirSrc) (void)hipFree(dMirSrc);
   }
 };
 
@@ -193,6 +214,9 @@ static wkern_status build_fft(const wkern_desc* d, int mode, size_t budget, wker
   pl->desc = *d;
   pl->support.assign(d->support, d->support + P);
   pl->desc.support = pl->support.data();
+  pl->mirror.assign(P, -1);
+  if (d->mirror) pl->mirror.assign(d->mirror, d->mirror + P);
+  pl->desc.mirror = pl->mirror.data();
   pl->offsets.resize(P + 1);
   wkern_status s = wkern_layout_desc(&pl->desc, pl->offsets.data(), nullptr);
   if (s != WKERN_OK) return s;
@@ -217,7 +241,8 @@ static wkern_status build_fft(const wkern_desc* d, int mode, size_t budget, wker
     if ((int64_t)g.L > 16384)
       return ffail(WKERN_ERR_UNSUPPORTED, "2D transform of %d^2 too large", g.L);
     for (int p = 0; p < P; ++p)
-      if (ws[p] == N) g.planes.push_back(p);
+      if (ws[p] == N && pl->mirror[p] < 0) g.planes.push_back(p);
+    if (g.planes.empty()) continue;
     g.first = (int)order.size();
     order.insert(order.end(), g.planes.begin(), g.planes.end());
     const size_t LL = (size_t)g.L * g.L;
@@ -253,11 +278,27 @@ static wkern_status build_fft(const wkern_desc* d, int mode, size_t budget, wker
   for (int p = 0; p < P; ++p) {
     const int S = d->support[p];
     const int h = (S - 1) / 2;
-    info[p] = FftPlane{pl->offsets[p], S, h, (os * h) * (os * h), 0};
+    info[p] = FftPlane{pl->offsets[p], S, h, (os * h) * (os * h), os * os * S * S};
   }
   FF_HIP(hipMalloc(&pl->dInfo, P * sizeof(FftPlane)), "plane table");
   FF_HIP(hipMemcpy(pl->dInfo, info.data(), P * sizeof(FftPlane), hipMemcpyHostToDevice),
          "plane table");
+  std::vector<int32_t> mir, src;
+  for (int p = 0; p < P; ++p)
+    if (pl->mirror[p] >= 0) {
+      mir.push_back(p);
+      src.push_back(pl->mirror[p]);
+    }
+  pl->nMirror = (int)mir.size();
+  if (pl->nMirror > 0) {
+    FF_HIP(hipMalloc(&pl->dMir, mir.size() * sizeof(int32_t)), "mirror table");
+    FF_HIP(hipMalloc(&pl->dMirSrc, src.size() * sizeof(int32_t)), "mirror table");
+    FF_HIP(hipMemcpy(pl->dMir, mir.data(), mir.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+           "mirror table");
+    FF_HIP(hipMemcpy(pl->dMirSrc, src.data(), src.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice),
+           "mirror table");
+  }
   return WKERN_OK;
 }
 
@@ -326,6 +367,12 @@ wkern_status wkern_fft2d_generate(wkern_fft2d_t plan, const float* taper, const 
                          plan->dPlanes, plan->dInfo, plan->work, (float2*)out);
       FF_HIP(hipGetLastError(), "extract launch");
     }
+  }
+  for (int m0 = 0; m0 < plan->nMirror; m0 += 65535) {
+    const int cnt = std::min(65535, plan->nMirror - m0);
+    hipLaunchKernelGGL(k_conj_copy, dim3(16, cnt), dim3(256), 0, st, cnt, plan->dMir + m0,
+                       plan->dMirSrc + m0, plan->dInfo, (float2*)out);
+    FF_HIP(hipGetLastError(), "conjugate copy launch");
   }
   (void)hipSetDevice(prev);
   return WKERN_OK;

@@ -30,12 +30,14 @@ constexpr int kSplineWarm = 32;
 // Per-plane table used by the resampler (caller order).
 struct PlaneInfo {
   int64_t out_off;    // complex64 offset of the plane's cache
-  int32_t line_off;   // offset of its radial line / spline intervals (sorted order)
+  int32_t line_off;   // offset of its (or its source plane's) radial line, sorted order
   int32_t nrho;       // radial nodes
   int32_t S;          // full width
   int32_t h;          // half width
   int32_t lim;        // (os h)^2
   float invS;         // 1 / S (estimate for the exact small division)
+  int32_t conj;       // 1: mirrored plane, written as the conjugate of its source
+  int32_t line_off_caller;  // offset of its own line in the caller-order layout
 };
 
 // One block of output elements [e0, e1) of plane p (plane-local indices).
@@ -81,7 +83,10 @@ constexpr int kChunkAlign = 128;
 
 struct DevPlan {
   // geometry
-  int P, Nr, NrPad, os, q, nrhoMax, rowsPad, colsPad, lineTotal, nkc, kchunk;
+  int P;           // computed planes (sorted order)
+  int Pall;        // all planes, mirrored ones included (caller order)
+  int lineTotalAll;  // sum of nrho over all planes
+  int Nr, NrPad, os, q, nrhoMax, rowsPad, colsPad, lineTotal, nkc, kchunk;
   int interp;     // 0 linear, 1 cubic
   int precision;  // 0 fp32, 1 bf16x6
   double dr, drho;
@@ -94,7 +99,10 @@ struct DevPlan {
   int32_t* lineOffSorted; // [P + 1]
   double* cprime;         // [nrhoMax] Thomas coefficients
   const int32_t* nrhoSortedHost;  // [P] host copy of nrhoSorted
-  PlaneInfo* planes;      // [P] caller order
+  PlaneInfo* planes;      // [Pall] caller order
+  int32_t* mirStart;      // [P + 1] mirrored planes of sorted plane j: mirList[mirStart[j] ..]
+  int32_t* mirList;       // [Pall - P] caller indices
+  int32_t* lineOffCaller; // [Pall + 1]
   ResampleUnit* units;
   int nUnits;
   // scratch
@@ -125,7 +133,6 @@ hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int
                            hipStream_t s);
 hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s);
 hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStream_t s);
-hipError_t launch_lines_out(const DevPlan& p, const int32_t* lineOffCaller, void* lines,
-                            hipStream_t s);
+hipError_t launch_lines_out(const DevPlan& p, void* lines, hipStream_t s);
 
 }  // namespace wkern

@@ -807,7 +807,9 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
         }
         const int X = os * (a - h) - fu;
         const int Y = os * (b - h) - fv;
-        __builtin_nontemporal_store(cache_value(X, Y, pi.lim, q, nmax, sc), o + e + lane);
+        f32x2 v = cache_value(X, Y, pi.lim, q, nmax, sc);
+        v.y = pi.conj ? -v.y : v.y;
+        __builtin_nontemporal_store(v, o + e + lane);
       }
       a0 += stepA;
       int c = stepR;
@@ -833,30 +835,29 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
       const int fv = div_small(F, os, invOs, fu);
       const int X = os * (a - h) - fu;
       const int Y = os * (b - h) - fv;
-      __builtin_nontemporal_store(cache_value(X, Y, pi.lim, q, nmax, sc), o + e);
+      f32x2 v = cache_value(X, Y, pi.lim, q, nmax, sc);
+      v.y = pi.conj ? -v.y : v.y;
+      __builtin_nontemporal_store(v, o + e);
     }
   }
 }
 
-// Radial lines in caller order (complex128), K-chunk partial sums combined.
-__global__ void k_lines_out(int P, int nkc, int lineTotal, const int32_t* __restrict__ perm,
-                            const int32_t* __restrict__ nrhoSorted,
-                            const int32_t* __restrict__ lineOffSorted,
-                            const int32_t* __restrict__ lineOffCaller,
+// Radial lines in caller order (complex128), K-chunk partial sums combined;
+// a mirrored plane gets the conjugate of its source's line.
+__global__ void k_lines_out(int Pall, int nkc, int lineTotal, const PlaneInfo* __restrict__ planes,
                             const double* __restrict__ part, double2* __restrict__ lines) {
-  const int j = blockIdx.y;
-  if (j >= P) return;
-  const int n = nrhoSorted[j];
-  const int so = lineOffSorted[j];
-  const int co = lineOffCaller[perm[j]];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+  const int p = blockIdx.y;
+  if (p >= Pall) return;
+  const PlaneInfo pi = planes[p];
+  const double sgn = pi.conj ? -1.0 : 1.0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < pi.nrho; k += gridDim.x * blockDim.x) {
     double re = 0.0, im = 0.0;
     for (int c = 0; c < nkc; ++c) {
-      const double2 v = ((const double2*)part)[(size_t)c * lineTotal + so + k];
+      const double2 v = ((const double2*)part)[(size_t)c * lineTotal + pi.line_off + k];
       re += v.x;
       im += v.y;
     }
-    lines[co + k] = make_double2(re, im);
+    lines[pi.line_off_caller + k] = make_double2(re, sgn * im);
   }
 }
 
@@ -867,7 +868,10 @@ __global__ void k_lines_out(int P, int nkc, int lineTotal, const int32_t* __rest
 // so the result is bit-reproducible.
 // ==========================================================================
 
-// Resample transpose, part 1: for interval k of plane p the moments
+// Resample transpose, part 1 (every plane, caller order, moments stored in the
+// caller-order line layout; a mirrored plane's cache is the conjugate of
+// its source's, so its gradient enters conjugated): for interval k of plane
+// p the moments
 //   g_j[k] = sum over cache samples e with interval(e) = k of u(e)^j G(e),
 // j = 0..3 (the gradients of the power-form coefficients c0..c3).  One
 // thread owns (k, fv, fu) and visits the rows b whose |Y| can reach the
@@ -944,7 +948,8 @@ __global__ __launch_bounds__(kMomThreads) void k_resample_T(
             float uu;
             radial_pos(d2, q, nmax, kk2, uu);
             if (kk2 != k) continue;
-            const float2 gv = gp[((size_t)(f * S + b)) * S + a];
+            float2 gv = gp[((size_t)(f * S + b)) * S + a];
+            if (pi.conj) gv.y = -gv.y;
             const double u1 = uu, u2 = u1 * u1, u3 = u2 * u1;
             m0.x += gv.x;
             m0.y += gv.y;
@@ -976,7 +981,7 @@ __global__ __launch_bounds__(kMomThreads) void k_resample_T(
         acc[j].x += v.x;
         acc[j].y += v.y;
       }
-    for (int j = 0; j < 4; ++j) mom[(size_t)(pi.line_off + k) * 4 + j] = acc[j];
+    for (int j = 0; j < 4; ++j) mom[(size_t)(pi.line_off_caller + k) * 4 + j] = acc[j];
   }
 }
 
@@ -986,15 +991,20 @@ __global__ __launch_bounds__(kMomThreads) void k_resample_T(
 // m = T^-1 D y, so dL/dy += D^T T^-T dL/dm, with T^T solved by Thomas
 // elimination.  One thread per sorted plane (complex arithmetic, real
 // coefficients).  gy, z and dp are FP64 complex scratch of the line layout.
-__global__ void k_spline_T(int P, int interp, const int32_t* __restrict__ nrhoSorted,
+__global__ void k_spline_T(int P, int interp, const int32_t* __restrict__ perm,
+                           const int32_t* __restrict__ nrhoSorted,
                            const int32_t* __restrict__ lineOffSorted,
+                           const int32_t* __restrict__ lineOffCaller,
+                           const int32_t* __restrict__ mirStart,
+                           const int32_t* __restrict__ mirList,
                            const double2* __restrict__ mom, double2* __restrict__ gy,
                            double2* __restrict__ gm, double2* __restrict__ dp) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= P) return;
   const int n = nrhoSorted[j];
   const size_t off = lineOffSorted[j];
-  const double2* M = mom + off * 4;
+  const double2* M = mom + (size_t)lineOffCaller[perm[j]] * 4;
+  const int m0 = mirStart[j], m1 = mirStart[j + 1];
   double2* y = gy + off;
   double2* m = gm + off;
   double2* d = dp + off;
@@ -1003,7 +1013,18 @@ __global__ void k_spline_T(int P, int interp, const int32_t* __restrict__ nrhoSo
     m[k] = make_double2(0, 0);
   }
   for (int k = 0; k < n; ++k) {
-    const double2 g0 = M[4 * k], g1 = M[4 * k + 1], g2 = M[4 * k + 2], g3 = M[4 * k + 3];
+    double2 g0 = M[4 * k], g1 = M[4 * k + 1], g2 = M[4 * k + 2], g3 = M[4 * k + 3];
+    for (int mi = m0; mi < m1; ++mi) {  // mirrored planes of this source
+      const double2* Mm = mom + (size_t)lineOffCaller[mirList[mi]] * 4;
+      g0.x += Mm[4 * k].x;
+      g0.y += Mm[4 * k].y;
+      g1.x += Mm[4 * k + 1].x;
+      g1.y += Mm[4 * k + 1].y;
+      g2.x += Mm[4 * k + 2].x;
+      g2.y += Mm[4 * k + 2].y;
+      g3.x += Mm[4 * k + 3].x;
+      g3.y += Mm[4 * k + 3].y;
+    }
     if (k == n - 1) {  // the last node's interval is the constant y_{n-1}
       y[k].x += g0.x;
       y[k].y += g0.y;
@@ -1119,6 +1140,13 @@ __global__ void k_grad_taper(int P, int Nr, int NrPad, const double* __restrict_
   double acc = 0.0;
   for (int j = 0; j < P; ++j) acc += ure[(size_t)j * NrPad + i];
   gtau[i] = (float)acc;
+}
+
+// dL/dw of mirrored planes is folded into their sources.
+__global__ void k_grad_w_mirrored(int n, const int32_t* __restrict__ mirList,
+                                  double* __restrict__ gw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) gw[mirList[i]] = 0.0;
 }
 
 // dL/dw_p = sum_i wterm[j][i]: per-thread strided sums, then a fixed tree.
@@ -1272,11 +1300,10 @@ hipError_t prepare_kernels(const DevPlan& p) {
   return hipSuccess;
 }
 
-hipError_t launch_lines_out(const DevPlan& p, const int32_t* lineOffCaller, void* lines,
-                            hipStream_t s) {
-  dim3 grid(4, p.P);
-  hipLaunchKernelGGL(k_lines_out, grid, dim3(256), 0, s, p.P, p.nkc, p.lineTotal, p.perm,
-                     p.nrhoSorted, p.lineOffSorted, lineOffCaller, p.part, (double2*)lines);
+hipError_t launch_lines_out(const DevPlan& p, void* lines, hipStream_t s) {
+  dim3 grid(4, p.Pall);
+  hipLaunchKernelGGL(k_lines_out, grid, dim3(256), 0, s, p.Pall, p.nkc, p.lineTotal, p.planes,
+                     p.part, (double2*)lines);
   return hipGetLastError();
 }
 
@@ -1291,13 +1318,14 @@ hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* tap
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
-  dim3 g1((p.nrhoMax + kpb - 1) / kpb, p.P);
+  dim3 g1((p.nrhoMax + kpb - 1) / kpb, p.Pall);
   hipLaunchKernelGGL(k_resample_T, g1, dim3(kMomThreads), shm, s, p.planes, p.os, (float)p.q,
                      (const float2*)gout, gs.mom);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_spline_T, dim3((p.P + 63) / 64), dim3(64), 0, s, p.P, p.interp,
-                     p.nrhoSorted, p.lineOffSorted, gs.mom, gs.gy, gs.gm, gs.dp);
+  hipLaunchKernelGGL(k_spline_T, dim3((p.P + 63) / 64), dim3(64), 0, s, p.P, p.interp, p.perm,
+                     p.nrhoSorted, p.lineOffSorted, p.lineOffCaller, p.mirStart, p.mirList,
+                     gs.mom, gs.gy, gs.gm, gs.dp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   dim3 g3((p.Nr + 255) / 256, p.P);
   hipLaunchKernelGGL(k_contract_T, g3, dim3(256), 0, s, p.Nr, p.NrPad, p.perm, p.nrhoSorted,
@@ -1307,7 +1335,14 @@ hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* tap
                      p.NrPad, gs.ure, gtau);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_grad_w, dim3(p.P), dim3(256), 0, s, p.Nr, p.NrPad, p.perm, gs.wterm, gw);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int nm = p.Pall - p.P;
+  if (nm > 0) {
+    hipLaunchKernelGGL(k_grad_w_mirrored, dim3((nm + 255) / 256), dim3(256), 0, s, nm, p.mirList,
+                       gw);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace wkern

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwkern.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 PRECISION = {"fp32": 0, "bf16x6": 1}
 INTERP = {"linear": 0, "cubic": 1}
 STATUS = {
@@ -60,6 +60,7 @@ class WkernDesc(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("interp", ctypes.c_int),
         ("device", ctypes.c_int32),
+        ("mirror", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -127,9 +128,10 @@ def _check(status: int) -> None:
 
 def make_desc(image_size: int, cellsize: float, n_radial: int, oversampling: int,
               support: Sequence[int], max_support: Optional[int] = None, radial_refine: int = 1,
-              precision: str = "fp32", interp: str = "cubic", device: int = 0):
-    """Build a WkernDesc; returns (desc, support array kept alive with it)."""
+              precision: str = "fp32", interp: str = "cubic", device: int = 0, mirror=None):
+    """Build a WkernDesc; returns (desc, arrays it points to, to be kept alive)."""
     sup = np.ascontiguousarray(np.asarray(support, dtype=np.int32))
+    mir = None if mirror is None else np.ascontiguousarray(np.asarray(mirror, dtype=np.int32))
     if max_support is None:
         max_support = int(sup.max()) if sup.size else 1
     d = WkernDesc()
@@ -145,7 +147,9 @@ def make_desc(image_size: int, cellsize: float, n_radial: int, oversampling: int
     d.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     d.interp = INTERP[interp] if isinstance(interp, str) else int(interp)
     d.device = int(device)
-    return d, sup
+    if mir is not None:
+        d.mirror = mir.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    return d, (sup, mir)
 
 
 def layout_desc(**kw):
@@ -178,10 +182,10 @@ class Plan:
     def __init__(self, image_size: int, cellsize: float, n_radial: int, oversampling: int,
                  support: Sequence[int], max_support: Optional[int] = None,
                  radial_refine: int = 1, precision: str = "fp32", interp: str = "cubic",
-                 device: int = 0):
+                 device: int = 0, mirror=None):
         lib = load_library()
-        d, sup = make_desc(image_size, cellsize, n_radial, oversampling, support, max_support,
-                           radial_refine, precision, interp, device)
+        d, (sup, mir) = make_desc(image_size, cellsize, n_radial, oversampling, support,
+                                  max_support, radial_refine, precision, interp, device, mirror)
         h = ctypes.c_void_p()
         _check(lib.wkern_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -189,6 +193,7 @@ class Plan:
         self.n_planes = int(d.n_planes)
         self.n_radial = int(n_radial)
         self.support = sup.copy()
+        self.mirror = None if mir is None else mir.copy()
         self.oversampling = int(oversampling)
         offs = np.zeros(self.n_planes + 1, dtype=np.int64)
         nrho = np.zeros(self.n_planes, dtype=np.int32)
@@ -199,10 +204,10 @@ class Plan:
 
     @classmethod
     def from_workload(cls, wl, precision: Optional[str] = None, interp: Optional[str] = None,
-                      device: int = 0) -> "Plan":
+                      device: int = 0, use_mirror: bool = True) -> "Plan":
         return cls(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, wl.support,
                    wl.max_support, wl.radial_refine, precision or wl.precision,
-                   interp or wl.interp, device)
+                   interp or wl.interp, device, wl.mirror if use_mirror else None)
 
     # ------------------------------------------------------------------
     def _check_inputs(self, taper, w):
@@ -320,10 +325,11 @@ class FFT2DPlan:
 
     def __init__(self, image_size: int, cellsize: float, n_radial: int, oversampling: int,
                  support: Sequence[int], max_support: Optional[int] = None,
-                 workspace: str = "max_support", workspace_bytes: int = 0, device: int = 0):
+                 workspace: str = "max_support", workspace_bytes: int = 0, device: int = 0,
+                 mirror=None):
         lib = load_library()
-        d, sup = make_desc(image_size, cellsize, n_radial, oversampling, support, max_support,
-                           1, "fp32", "cubic", device)
+        d, (sup, mir) = make_desc(image_size, cellsize, n_radial, oversampling, support,
+                                  max_support, 1, "fp32", "cubic", device, mirror)
         h = ctypes.c_void_p()
         _check(lib.wkern_fft2d_plan(ctypes.byref(d), self.WORKSPACE[workspace],
                                     int(workspace_bytes), ctypes.byref(h)))
@@ -335,9 +341,10 @@ class FFT2DPlan:
                                       max_support=d.max_support)
 
     @classmethod
-    def from_workload(cls, wl, workspace: str = "max_support", device: int = 0):
+    def from_workload(cls, wl, workspace: str = "max_support", device: int = 0,
+                      use_mirror: bool = True):
         return cls(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, wl.support,
-                   wl.max_support, workspace, 0, device)
+                   wl.max_support, workspace, 0, device, wl.mirror if use_mirror else None)
 
     def generate(self, taper, w, out=None, stream=None):
         import torch

@@ -115,3 +115,22 @@ def test_plan_without_device_fails_cleanly(lib):
     with pytest.raises(lib_mod.WkernError) as ei:
         lib_mod.Plan(128, 7.8125e-4, 64, 4, [7])
     assert ei.value.status == 3
+
+
+@pytest.mark.parametrize("mirror", [[0, -1], [-1, 5], [-1, 0, 1], [2, -1, -1], [-2, -1]])
+def test_invalid_mirror_tables(lib, mirror):
+    sup = [7, 7, 9][:len(mirror)]
+    with pytest.raises(lib_mod.WkernError) as ei:
+        lib_mod.layout_desc(image_size=128, cellsize=7.8125e-4, n_radial=64, oversampling=4,
+                            support=sup, max_support=9, mirror=mirror)
+    assert ei.value.status == 1
+
+
+def test_mirror_table_of_batch_workload():
+    wl = W.batch()
+    m = wl.mirror
+    assert (m >= 0).sum() == wl.n_planes // 2
+    src = m[m >= 0]
+    assert np.all(m[src] == -1)
+    assert np.all(wl.w[m >= 0] == -wl.w[src])
+    assert np.all(wl.support[m >= 0] == wl.support[src])

@@ -52,3 +52,10 @@ def test_random_ragged(workspace):
 
 def test_paper_sampled():
     _run(W.paper(), "max_support", planes=[0, 90, 255])
+
+
+def test_mirrored_planes():
+    base = W.plain()
+    wl = W.plain(extra_w=[-v for v in base.w])
+    wl.mirror = W.mirror_table(wl.w, wl.support)
+    _run(wl, "per_plane")

@@ -155,3 +155,36 @@ def test_device_adjoint_dot_product():
     print(f"dot product: {lhs:.9e} vs {rhs:.9e}", flush=True)
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
     plan.close()
+
+
+def test_grad_with_mirrored_planes():
+    """With mirror[p] = q the cache of p is conj K(w_q): dL/dtaper is unchanged,
+    dL/dw_q = dL/dw_q - dL/dw_p of the independent-plane oracle gradient
+    (d(-w_q) = -dw_q), and dL/dw_p = 0."""
+    from paper_1904_08463_amd import Plan
+    wl = W.random_small(41, n_planes=6, n_radial=200, os_=3, max_support=21)
+    w2 = np.concatenate([wl.w, -wl.w])
+    sup2 = np.concatenate([wl.support, wl.support]).astype(np.int32)
+    mir = W.mirror_table(w2, sup2)
+    assert (mir >= 0).sum() == 6
+    plan = Plan(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, sup2, wl.max_support,
+                mirror=mir)
+    rng = np.random.default_rng(11)
+    total = int(plan.offsets[-1])
+    g = (rng.normal(size=total) + 1j * rng.normal(size=total)).astype(np.complex64)
+    gt, gw = plan.grad(torch.from_numpy(wl.taper).cuda(), torch.from_numpy(w2).cuda(),
+                       torch.from_numpy(g).cuda())
+    gt, gw = gt.cpu().numpy().astype(np.float64), gw.cpu().numpy()
+    g_caches = [g[plan.offsets[p]:plan.offsets[p + 1]].astype(np.complex128).reshape(
+        wl.oversampling, wl.oversampling, sup2[p], sup2[p]) for p in range(len(w2))]
+    gt_ref, gw_ref = A.grad(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling,
+                            wl.taper.astype(np.float64), w2, sup2, g_caches)
+    want = gw_ref.copy()
+    for p in range(len(w2)):
+        if mir[p] >= 0:
+            want[mir[p]] -= gw_ref[p]
+            want[p] = 0.0
+    print(f"mirrors: taper err {_rel(gt, gt_ref):.2e}, w err {_rel(gw, want):.2e}", flush=True)
+    assert _rel(gt, gt_ref) <= GATE and _rel(gw, want) <= GATE
+    assert np.all(gw[mir >= 0] == 0.0)
+    plan.close()

@@ -52,6 +52,7 @@ class Workload:
     interp: str = "cubic"    # "cubic" | "linear"
     taper_fn: object = field(default=None, repr=False)  # callable of r (radians) or None
     notes: str = ""
+    mirror: object = field(default=None, repr=False)  # int32 [P]: -1 or the plane with -w
 
     @property
     def n_planes(self) -> int:
@@ -60,6 +61,24 @@ class Workload:
     @property
     def r_max(self) -> float:
         return 0.5 * self.image_size * self.cellsize
+
+
+def mirror_table(w: np.ndarray, support: np.ndarray) -> np.ndarray:
+    """Pairs planes whose w values are exact negatives of each other (same
+    support): the later plane of a pair gets the index of the earlier one,
+    every other plane -1.  w = 0 is never paired."""
+    w = np.asarray(w, dtype=np.float64)
+    mir = np.full(w.shape[0], -1, dtype=np.int32)
+    open_ = {}  # (w, support) of an unpaired plane -> its index
+    for p in range(w.shape[0]):
+        if w[p] == 0.0:
+            continue
+        q = open_.pop((float(-w[p]), int(support[p])), None)
+        if q is not None:
+            mir[p] = q
+        else:
+            open_.setdefault((float(w[p]), int(support[p])), p)
+    return mir
 
 
 def nodes_nu(n_radial: int) -> np.ndarray:
@@ -179,11 +198,13 @@ def batch(n_w: int = 1024, n_chan: int = 16, n_radial: int = 8192,
     w = batch_w(n_w, n_chan)
     h = 3 + np.rint(124.0 * np.abs(w) / np.max(np.abs(w))).astype(np.int64)
     fn = spheroidal_taper(r_max)
+    sup = (2 * h + 1).astype(np.int32)
     return Workload(
         name="batch", image_size=n, cellsize=cell, n_radial=n_radial, oversampling=8,
-        radial_refine=1, w=w, support=(2 * h + 1).astype(np.int32), max_support=255,
+        radial_refine=1, w=w, support=sup, max_support=255,
         taper=sample_taper(fn, n_radial, r_max), precision=precision, taper_fn=fn,
-        notes="16 ch x 1024 w, 1/|w| density on +-[40,40000], S = 7..255")
+        notes="16 ch x 1024 w, 1/|w| density on +-[40,40000], S = 7..255",
+        mirror=mirror_table(w, sup))
 
 
 def grad(n_planes: int = 256, n_radial: int = 2048, noise: float = 1e-3,
