@@ -481,8 +481,9 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   g.nrhoSortedHost = pl->nrhoSorted.data();
   g.nrhoMax = nrhoSorted[0];
   g.rowsPad = (int)round_up(g.nrhoMax, kRowAlign);
-  // column blocks of a chunk may run up to 256 columns past its last plane
-  g.colsPad = (int)round_up(2 * (int64_t)Pc, kColAlign) + 256;
+  // column blocks of a chunk may run up to 512 columns (the widest tile) past
+  // its last plane
+  g.colsPad = (int)round_up(2 * (int64_t)Pc, kColAlign) + 512;
 
   // K-chunks: the longest power-of-two multiple of 256 dividing NrPad, <= 2048
   g.kchunk = kNrAlign;
@@ -571,6 +572,10 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
     WK_HIP(hipEventCreate(&b), "hipEventCreate");
     float best = 1e30f;
     for (int v = 0; v < kNumVariants; ++v) {
+      if (!variant_supported(g.precision, v)) {
+        pl->variantMs[v] = -1.f;
+        continue;
+      }
       const int nt = pl->chunkT[v].back();
       float bestV = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
@@ -800,6 +805,8 @@ wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant) {
   if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
   if (variant < 0 || variant >= kNumVariants)
     return fail(WKERN_ERR_INVALID_ARG, "variant %d not in [0, %d)", variant, kNumVariants);
+  if (!variant_supported(plan->dp.precision, variant))
+    return fail(WKERN_ERR_INVALID_ARG, "variant %d is not available for this precision", variant);
   plan->variant = variant;
   plan->graphValid = false;
   return WKERN_OK;

@@ -66,7 +66,12 @@ enum ContractVariant {
   kWave32x128 = 1,  // one wave per tile of 32 rows x 128 columns, direct loads
   kLds128x128 = 2,  // 4 waves, up to 128 rows of M staged in LDS, 128 columns
   kLds64x256 = 3,   // 4 waves, up to 64 rows of M staged in LDS, 256 columns
-  kNumVariants = 4
+  // split-BF16 only: M rows and screen columns through a ring of LDS stages
+  // filled by direct global-to-LDS loads
+  kRing128x128 = 4,
+  kRing64x256 = 5,
+  kRing32x512 = 6,
+  kNumVariants = 7
 };
 
 // Tile geometry of a variant: rows per tile = 32 * rb, columns per tile.
@@ -76,6 +81,10 @@ struct ContractShape {
   int pad;
 };
 ContractShape contract_shape(int variant);
+// The ring variants exist for the split-BF16 contraction only.
+inline bool variant_supported(int precision, int variant) {
+  return variant < kRing128x128 || precision == 1;
+}
 
 // Planes of a pipeline chunk start at multiples of this (in sorted order),
 // so no contraction column block straddles two chunks.

@@ -271,7 +271,8 @@ class Plan:
         _check(load_library().wkern_stage_times(self._h, ms, ctypes.byref(calls)))
         return dict(zip(self.STAGES, list(ms))), calls.value
 
-    VARIANTS = ("wave32x64", "wave32x128", "lds128x128", "lds64x256")
+    VARIANTS = ("wave32x64", "wave32x128", "lds128x128", "lds64x256", "ring128x128",
+                "ring64x256", "ring32x512")
 
     def info(self):
         """Autotuner choice, candidate timings (ms) and pipeline chunk count."""

@@ -182,12 +182,16 @@ def test_batch_workload_full_size(precision):
     plan.close()
 
 
-VARIANTS = ("wave32x64", "wave32x128", "lds128x128", "lds64x256")
+VARIANTS = ("wave32x64", "wave32x128", "lds128x128", "lds64x256", "ring128x128", "ring64x256",
+            "ring32x512")
+SPLIT_ONLY = ("ring128x128", "ring64x256", "ring32x512")
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_every_contraction_variant(variant, precision):
+    if precision == "fp32" and variant in SPLIT_ONLY:
+        pytest.skip("split-BF16 only variant")
     """Every candidate the autotuner may pick, on ragged random planes and on
     sampled planes of the paper workload."""
     for wl, planes in ((W.random_small(5, n_planes=45, n_radial=300, os_=5, max_support=41), None),
