@@ -39,6 +39,9 @@ def _parse():
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-fft", action="store_true")
     ap.add_argument("--fft-steps", type=int, default=2)
+    ap.add_argument("--profile", action="store_true",
+                    help="counter pass: one warm and one measured generate of the split path, "
+                         "then a 2 GiB device copy as the reference for the byte counters")
     return ap.parse_args()
 
 
@@ -108,6 +111,28 @@ def _fft_paths(wl, taper, w, out, steps):
     return res
 
 
+def _profile_pass(wl):
+    """Kernels for a hardware-counter run: two generate calls of the split path
+    and a plain 2 GiB device-to-device copy of known size."""
+    import torch
+    from paper_1904_08463_amd import Plan
+    taper = torch.from_numpy(wl.taper).cuda()
+    w = torch.from_numpy(wl.w).cuda()
+    plan = Plan.from_workload(wl, precision="bf16x6")
+    out = torch.empty(int(plan.offsets[-1]), dtype=torch.complex64, device="cuda")
+    for _ in range(2):
+        plan.generate(taper, w, out)
+    torch.cuda.synchronize()
+    plan.close()
+    del out
+    src = torch.ones(1 << 28, dtype=torch.float64, device="cuda")  # 2 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_pass": "done", "output_bytes": int(plan.offsets[-1]) * 8,
+                      "copy_bytes": 2 * (1 << 30)}), flush=True)
+
+
 def _cpu_baseline(wl, stride):
     """The FP64 oracle, as it stands, on a stratified sample of the planes."""
     from oracle import hankel as H
@@ -146,6 +171,9 @@ def main():
 
     torch.cuda.set_device(0)
     wl = W.batch()
+    if args.profile:
+        _profile_pass(wl)
+        return
     taper = torch.from_numpy(wl.taper).cuda()
     w = torch.from_numpy(wl.w).cuda()
 

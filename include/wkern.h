@@ -138,6 +138,28 @@ wkern_status wkern_layout(wkern_plan_t plan, int64_t* offsets, int32_t* nrho);
 wkern_status wkern_generate(wkern_plan_t plan, const float* taper, const double* w,
                             void* out, void* stream);
 
+/* Generation with the truncation step of Algorithm 2 (section 3.1: the
+ * 1D conv-kernel is cut where its amplitude falls below a fraction of its
+ * maximum).  The plan's support S_p is plane p's maximum.  Every line is
+ * computed for it; k* is the last radial node with
+ * |K_p(rho_k)| >= frac * max_k |K_p(rho_k)| (FP64); the plane gets the
+ * half-width h_p = min(ceil(k* / (q os)), (S_p - 1) / 2) and its cache is
+ * sampled from the spline through the full line, over the circular support
+ * of h_p.  A mirrored plane takes its source's support.
+ * frac:        in (0, 1), e.g. 0.01.
+ * out:         device complex64 [out_capacity]; the planes are packed in
+ *              caller order at offsets_out (elements beyond offsets_out[P]
+ *              are not written).
+ * out_capacity: >= the untruncated cache size (offsets[P] of wkern_layout),
+ *              so no truncation outcome can overflow it.
+ * support_out: device int32 [P] (written): the truncated full widths.
+ * offsets_out: device int64 [P + 1] (written): prefix sums of os^2 S^2.
+ * Asynchronous on `stream` (the layout is known once the stream reaches
+ * this point).  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+wkern_status wkern_generate_truncated(wkern_plan_t plan, const float* taper, const double* w,
+                                      double frac, void* out, int64_t out_capacity,
+                                      int32_t* support_out, int64_t* offsets_out, void* stream);
+
 /* Steps 1-2 only: the radial lines, for inspection and tests.
  * lines: device complex128 (two doubles) [sum_p nrho[p]], plane p's line at
  * the prefix sum of nrho over planes before p (caller order); line p holds

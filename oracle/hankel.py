@@ -33,6 +33,13 @@ R9  Radial uv nodes rho_k = k du / (q os), q >= 1 (q = 1 is the spacing du/os
     the 1D zero padding by os gives), k = 0 .. q os h + 3.
 R10 Cubic spline: interpolating, s'(0) = 0 (radial symmetry), natural
     (s'' = 0) at the last node; linear option = piecewise linear.
+R11 Truncation (section 3.1 and Algorithm 2: the 1D conv-kernel is cut
+    where its amplitude falls below a fraction f, default 1%, of its
+    maximum): on the radial line computed for the maximum support, k* is
+    the last node with |K(rho_k)| >= f max_k |K(rho_k)|; the plane's
+    half-width is h = ceil(k* / (q os)) uv cells (so the circular support
+    reaches rho_{k*}), clamped to the maximum half-width.  The cache is then
+    sampled from the spline through the full line.
 """
 from __future__ import annotations
 
@@ -232,6 +239,37 @@ def generate(image_size, cellsize, n_radial, oversampling, taper, w, support,
     caches = [resample(lines[j], int(support[p]), oversampling, radial_refine, interp)
               for j, p in enumerate(idx)]
     return caches, lines
+
+
+def truncated_half_support(line: np.ndarray, frac: float, oversampling: int,
+                           radial_refine: int, h_max: int) -> int:
+    """Half-width after truncation at `frac` of the maximum amplitude (R11)."""
+    amp = np.abs(np.asarray(line))
+    above = np.nonzero(amp >= frac * amp.max())[0]
+    k_star = int(above[-1])
+    h = -(-k_star // (radial_refine * oversampling))  # ceil
+    return min(h, h_max)
+
+
+def generate_truncated(image_size, cellsize, n_radial, oversampling, taper, w, max_support,
+                       frac: float = 0.01, radial_refine: int = 1, interp: str = "cubic",
+                       planes=None):
+    """Algorithm 2 with the truncation step: every plane's radial line is
+    computed for the maximum support, its support is chosen by R11, and its
+    cache is sampled from the spline through the full line.  Returns
+    (caches, supports, lines)."""
+    geo = geometry(image_size, cellsize, n_radial, oversampling, radial_refine)
+    w = np.asarray(w, dtype=np.float64)
+    idx = np.arange(len(w)) if planes is None else np.asarray(planes)
+    h_max = (max_support - 1) // 2
+    lines = radial_kernels(geo, taper, w[idx], np.full(len(idx), max_support))
+    supports, caches = [], []
+    for line in lines:
+        h = truncated_half_support(line, frac, oversampling, radial_refine, h_max)
+        s = 2 * h + 1
+        supports.append(s)
+        caches.append(resample(line, s, oversampling, radial_refine, interp))
+    return caches, np.asarray(supports, dtype=np.int32), lines
 
 
 def generate_workload(wl, planes=None, interp=None):

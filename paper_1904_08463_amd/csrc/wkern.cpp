@@ -180,6 +180,11 @@ struct wkern_plan_s {
   const void* graphKey[3] = {nullptr, nullptr, nullptr};
   bool graphValid = false;
 
+  // truncated generation scratch, allocated on its first call
+  TruncScratch trunc{};
+  bool truncReady = false;
+  std::vector<int32_t> sortedPosOfCaller;  // [Pall] sorted index of the plane's source
+
   // adjoint scratch, allocated on the first wkern_grad call
   GradScratch grad{};
   bool gradReady = false;
@@ -509,6 +514,9 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   }
 
   pl->perm = perm;
+  pl->sortedPosOfCaller.resize(P);
+  for (int p = 0; p < P; ++p)
+    pl->sortedPosOfCaller[p] = sortedPos[pl->mirror[p] >= 0 ? pl->mirror[p] : p];
 
   // Thomas coefficients of the spline system: c'_0 = 1/2, c'_k = 1/(4 - c'_{k-1})
   std::vector<double> cprime(std::max(g.nrhoMax, 1));
@@ -757,6 +765,38 @@ wkern_status wkern_set_graph(wkern_plan_t plan, int32_t enable) {
   clear_error();
   if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
   plan->useGraph = enable != 0;
+  return WKERN_OK;
+}
+
+wkern_status wkern_generate_truncated(wkern_plan_t plan, const float* taper, const double* w,
+                                      double frac, void* out, int64_t out_capacity,
+                                      int32_t* support_out, int64_t* offsets_out, void* stream) {
+  clear_error();
+  wkern_status s = check_gen_args(plan, taper, w, out);
+  if (s != WKERN_OK) return s;
+  if (!support_out || !offsets_out) return fail(WKERN_ERR_INVALID_ARG, "layout output is NULL");
+  if (!(frac > 0.0 && frac < 1.0)) return fail(WKERN_ERR_INVALID_ARG, "frac %g not in (0, 1)", frac);
+  if (out_capacity < plan->offsets.back())
+    return fail(WKERN_ERR_INVALID_ARG, "out_capacity %lld < %lld (untruncated cache)",
+                (long long)out_capacity, (long long)plan->offsets.back());
+  DeviceGuard guard(plan->desc.device);
+  const DevPlan& g = plan->dp;
+  if (!plan->truncReady) {
+    TruncScratch& ts = plan->trunc;
+    if ((s = plan->alloc(&ts.hTrunc, (size_t)g.P, "truncation table")) != WKERN_OK) return s;
+    if ((s = plan->alloc(&ts.unitStart, (size_t)g.Pall + 1, "truncation table")) != WKERN_OK)
+      return s;
+    if ((s = plan->upload(&ts.sortedPos, plan->sortedPosOfCaller, "truncation table")) != WKERN_OK)
+      return s;
+    plan->truncReady = true;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int v = plan->variant;
+  WK_HIP(launch_screen(g, 0, g.P, taper, w, st), "screen launch");
+  WK_HIP(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
+         "contraction launch");
+  WK_HIP(launch_resample_truncated(g, plan->trunc, frac, support_out, offsets_out, out, st),
+         "truncated resample launch");
   return WKERN_OK;
 }
 

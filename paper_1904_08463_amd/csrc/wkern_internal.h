@@ -140,7 +140,18 @@ hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, c
                          hipStream_t s);
 hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int nTiles,
                            hipStream_t s);
-hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s);
+hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s, double frac = 0.0,
+                         int32_t* hTrunc = nullptr);
+
+// Scratch of the truncated generation (allocated on its first call).
+struct TruncScratch {
+  int32_t* hTrunc;     // [P] truncated half-widths (sorted order)
+  int32_t* sortedPos;  // [Pall] caller plane -> sorted index of its source
+  int32_t* unitStart;  // [Pall + 1] prefix sums of resample units
+};
+hipError_t launch_resample_truncated(const DevPlan& p, const TruncScratch& ts, double frac,
+                                     int32_t* supportOut, int64_t* offsetsOut, void* out,
+                                     hipStream_t s);
 hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStream_t s);
 hipError_t launch_lines_out(const DevPlan& p, void* lines, hipStream_t s);
 

@@ -771,7 +771,8 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
                                                const int32_t* __restrict__ lineOffSorted,
                                                const double* __restrict__ cprime,
                                                const double* __restrict__ part,
-                                               float4* __restrict__ coef) {
+                                               float4* __restrict__ coef, double frac2,
+                                               int qos, int32_t* __restrict__ hTrunc) {
   extern __shared__ double2 smem[];
   const int j = j0 + blockIdx.x;
   const int lane = threadIdx.x;
@@ -791,6 +792,19 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
     y[k] = make_double2(re, im);
   }
   __syncthreads();
+
+  if (hTrunc) {
+    // truncation (section 3.1): last node with |y_k|^2 >= frac^2 max |y|^2;
+    // half-width ceil(k* / (q os)), at most the planned (n - 4) / (q os)
+    double mx = 0.0;
+    for (int k = lane; k < n; k += 64) mx = fmax(mx, y[k].x * y[k].x + y[k].y * y[k].y);
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    int last = 0;
+    for (int k = lane; k < n; k += 64)
+      if (y[k].x * y[k].x + y[k].y * y[k].y >= frac2 * mx) last = max(last, k);
+    for (int o = 32; o > 0; o >>= 1) last = max(last, __shfl_xor(last, o));
+    if (lane == 0) hTrunc[j] = min((last + qos - 1) / qos, (n - 4) / qos);
+  }
 
   const int L = (n + 63) / 64;
   const int s = min(lane * L, n);
@@ -922,17 +936,11 @@ __device__ __forceinline__ int div_small(int n, int d, float inv, int& rem) {
   return qt;
 }
 
-__global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict__ units,
-                                                  const PlaneInfo* __restrict__ planes,
-                                                  const float4* __restrict__ coef, int os,
-                                                  float invOs, float q,
-                                                  float2* __restrict__ out) {
-  extern __shared__ float4 sc[];
-  const ResampleUnit u = units[blockIdx.x];
-  const PlaneInfo pi = planes[u.p];
-  const float4* src = coef + (size_t)pi.line_off * 2;
-  for (int k = threadIdx.x; k < pi.nrho * 2; k += 256) sc[k] = src[k];
-  __syncthreads();
+// Writes elements [e0, e1) of one plane (its spline intervals already in sc).
+__device__ __forceinline__ void resample_range(const PlaneInfo& pi, int e0, int e1, int os,
+                                               float invOs, float q,
+                                               const float4* __restrict__ sc,
+                                               float2* __restrict__ out) {
   f32x2* o = (f32x2*)(out + pi.out_off);
   const int S = pi.S;
   const int h = pi.h;
@@ -943,7 +951,7 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
     // element is decoded once (wave-uniform) and advanced by 256 elements per
     // step; within a chunk a row boundary is crossed at most once.
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int e = u.e0 + 64 * wave;
+    int e = e0 + 64 * wave;
     int R = e / S;
     int a0 = e - R * S;
     int F = R / S;
@@ -952,8 +960,8 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
     int fu0 = F - fv0 * os;
     const int stepA = 256 % S;
     const int stepR = 256 / S;
-    for (; e < u.e1; e += 256) {
-      if (e + lane < u.e1) {
+    for (; e < e1; e += 256) {
+      if (e + lane < e1) {
         int a = a0 + lane;
         int b = b0, fu = fu0, fv = fv0;
         if (a >= S) {
@@ -991,7 +999,7 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
       }
     }
   } else {
-    for (int e = u.e0 + (int)threadIdx.x; e < u.e1; e += 256) {
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
       int a, b, fu;
       const int R = div_small(e, S, pi.invS, a);
       const int F = div_small(R, S, pi.invS, b);
@@ -1002,6 +1010,121 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
       v.y = pi.conj ? -v.y : v.y;
       __builtin_nontemporal_store(v, o + e);
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict__ units,
+                                                  const PlaneInfo* __restrict__ planes,
+                                                  const float4* __restrict__ coef, int os,
+                                                  float invOs, float q,
+                                                  float2* __restrict__ out) {
+  extern __shared__ float4 sc[];
+  const ResampleUnit u = units[blockIdx.x];
+  const PlaneInfo pi = planes[u.p];
+  const float4* src = coef + (size_t)pi.line_off * 2;
+  for (int k = threadIdx.x; k < pi.nrho * 2; k += 256) sc[k] = src[k];
+  __syncthreads();
+  resample_range(pi, u.e0, u.e1, os, invOs, q, sc, out);
+}
+
+// Truncated layout (section 3.1, Algorithm 2): one block of 1024 threads.
+// Plane p (caller order) takes the half-width its source line was truncated
+// to; writes supports, the exclusive prefix sums of os^2 S^2 (offsets) and
+// of the per-plane resample units (unitStart, units of kUnitElems).
+constexpr int kUnitElems = 65536;
+
+__global__ __launch_bounds__(1024) void k_trunc_layout(int Pall, int os,
+                                                       const int32_t* __restrict__ hSorted,
+                                                       const int32_t* __restrict__ sortedPos,
+                                                       int32_t* __restrict__ supportOut,
+                                                       int64_t* __restrict__ offsetsOut,
+                                                       int32_t* __restrict__ unitStart) {
+  __shared__ int64_t sBytes[1024];
+  __shared__ int32_t sUnits[1024];
+  __shared__ int64_t carryB;
+  __shared__ int32_t carryU;
+  if (threadIdx.x == 0) {
+    carryB = 0;
+    carryU = 0;
+  }
+  __syncthreads();
+  for (int base = 0; base < Pall; base += 1024) {
+    const int p = base + (int)threadIdx.x;
+    int64_t n = 0;
+    int32_t nu = 0;
+    if (p < Pall) {
+      const int S = 2 * hSorted[sortedPos[p]] + 1;
+      supportOut[p] = S;
+      n = (int64_t)os * os * S * S;
+      nu = (int32_t)((n + kUnitElems - 1) / kUnitElems);
+    }
+    sBytes[threadIdx.x] = n;
+    sUnits[threadIdx.x] = nu;
+    __syncthreads();
+    // inclusive scan (Hillis-Steele) in a fixed order
+    for (int d = 1; d < 1024; d <<= 1) {
+      int64_t tb = 0;
+      int32_t tu = 0;
+      if ((int)threadIdx.x >= d) {
+        tb = sBytes[threadIdx.x - d];
+        tu = sUnits[threadIdx.x - d];
+      }
+      __syncthreads();
+      sBytes[threadIdx.x] += tb;
+      sUnits[threadIdx.x] += tu;
+      __syncthreads();
+    }
+    if (p < Pall) {
+      offsetsOut[p] = carryB + sBytes[threadIdx.x] - n;
+      unitStart[p] = carryU + sUnits[threadIdx.x] - nu;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) {
+      carryB += sBytes[1023];
+      carryU += sUnits[1023];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    offsetsOut[Pall] = carryB;
+    unitStart[Pall] = carryU;
+  }
+}
+
+// Resample of a truncated layout: a fixed grid walks the units; unit u
+// belongs to the plane found by binary search in unitStart.
+__global__ __launch_bounds__(256) void k_resample_trunc(int Pall, const PlaneInfo* __restrict__ planes,
+                                                        const int32_t* __restrict__ supportOut,
+                                                        const int64_t* __restrict__ offsetsOut,
+                                                        const int32_t* __restrict__ unitStart,
+                                                        const float4* __restrict__ coef, int os,
+                                                        float invOs, float q,
+                                                        float2* __restrict__ out) {
+  extern __shared__ float4 sc[];
+  const int total = unitStart[Pall];
+  for (int u = blockIdx.x; u < total; u += gridDim.x) {
+    int lo = 0, hi = Pall - 1;  // last p with unitStart[p] <= u
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (unitStart[mid] <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    const int p = lo;
+    PlaneInfo pi = planes[p];
+    const int S = supportOut[p];
+    pi.S = S;
+    pi.h = (S - 1) / 2;
+    pi.lim = (os * pi.h) * (os * pi.h);
+    pi.invS = 1.0f / (float)S;
+    pi.out_off = offsetsOut[p];
+    const int n = os * os * S * S;
+    const int e0 = (u - unitStart[p]) * kUnitElems;
+    const int e1 = min(n, e0 + kUnitElems);
+    __syncthreads();  // the previous unit is done with sc
+    const float4* src = coef + (size_t)pi.line_off * 2;
+    for (int k = threadIdx.x; k < pi.nrho * 2; k += 256) sc[k] = src[k];
+    __syncthreads();
+    resample_range(pi, e0, e1, os, invOs, q, sc, out);
   }
 }
 
@@ -1441,7 +1564,8 @@ hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int
   return hipGetLastError();
 }
 
-hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s) {
+hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s, double frac,
+                         int32_t* hTrunc) {
   // Planes are sorted by radial length (longest first); each launch covers a
   // run of planes whose lines fit its LDS size, so short lines are not
   // limited to the occupancy of the longest one.
@@ -1455,7 +1579,8 @@ hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s) {
     const int nmax = p.nrhoSortedHost[j0] < cap ? p.nrhoSortedHost[j0] : cap;
     const size_t shm = (size_t)3 * nmax * sizeof(double2);
     hipLaunchKernelGGL(k_spline, dim3(jb - j0), dim3(64), shm, s, j0, p.nkc, p.lineTotal,
-                       p.interp, p.nrhoSorted, p.lineOffSorted, p.cprime, p.part, p.coef);
+                       p.interp, p.nrhoSorted, p.lineOffSorted, p.cprime, p.part, p.coef,
+                       frac * frac, p.q * p.os, hTrunc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     j0 = jb;
@@ -1481,6 +1606,21 @@ hipError_t prepare_kernels(const DevPlan& p) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_resample_truncated(const DevPlan& p, const TruncScratch& ts, double frac,
+                                     int32_t* supportOut, int64_t* offsetsOut, void* out,
+                                     hipStream_t s) {
+  hipError_t e = launch_spline(p, 0, p.P, s, frac, ts.hTrunc);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_trunc_layout, dim3(1), dim3(1024), 0, s, p.Pall, p.os, ts.hTrunc,
+                     ts.sortedPos, supportOut, offsetsOut, ts.unitStart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t shm = (size_t)2 * p.nrhoMax * sizeof(float4);
+  hipLaunchKernelGGL(k_resample_trunc, dim3(2048), dim3(256), shm, s, p.Pall, p.planes, supportOut,
+                     offsetsOut, ts.unitStart, p.coef, p.os, 1.0f / (float)p.os, (float)p.q,
+                     (float2*)out);
+  return hipGetLastError();
 }
 
 hipError_t launch_lines_out(const DevPlan& p, void* lines, hipStream_t s) {

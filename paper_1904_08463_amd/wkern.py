@@ -31,7 +31,7 @@ STATUS = {
 # every symbol include/wkern.h declares
 EXPORTS = (
     "wkern_abi_version", "wkern_layout_desc", "wkern_plan", "wkern_layout",
-    "wkern_generate", "wkern_generate_radial", "wkern_grad", "wkern_set_profiling",
+    "wkern_generate", "wkern_generate_truncated", "wkern_generate_radial", "wkern_grad", "wkern_set_profiling",
     "wkern_stage_times", "wkern_plan_info", "wkern_set_variant",
     "wkern_set_chunks", "wkern_set_graph", "wkern_destroy",
     "wkern_strerror", "wkern_last_error",
@@ -87,6 +87,9 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_layout.argtypes = [vp, i64p, i32p]
     lib.wkern_generate.restype = ctypes.c_int
     lib.wkern_generate.argtypes = [vp, vp, vp, vp, vp]
+    lib.wkern_generate_truncated.restype = ctypes.c_int
+    lib.wkern_generate_truncated.argtypes = [vp, vp, vp, ctypes.c_double, vp, ctypes.c_int64, vp,
+                                             vp, vp]
     lib.wkern_generate_radial.restype = ctypes.c_int
     lib.wkern_generate_radial.argtypes = [vp, vp, vp, vp, vp]
     lib.wkern_grad.restype = ctypes.c_int
@@ -231,6 +234,21 @@ class Plan:
         _check(load_library().wkern_generate(self._h, _ptr(taper), _ptr(w), _ptr(out),
                                              _stream_handle(stream)))
         return out
+
+    def generate_truncated(self, taper, w, frac=0.01, out=None, stream=None):
+        """Truncated generation: (flat complex64 cache of the untruncated size,
+        int32 supports [P], int64 offsets [P + 1]) on the device."""
+        import torch
+        self._check_inputs(taper, w)
+        total = int(self.offsets[-1])
+        if out is None:
+            out = torch.empty(total, dtype=torch.complex64, device=taper.device)
+        sup = torch.empty(self.n_planes, dtype=torch.int32, device=taper.device)
+        offs = torch.empty(self.n_planes + 1, dtype=torch.int64, device=taper.device)
+        _check(load_library().wkern_generate_truncated(
+            self._h, _ptr(taper), _ptr(w), ctypes.c_double(frac), _ptr(out),
+            ctypes.c_int64(out.numel()), _ptr(sup), _ptr(offs), _stream_handle(stream)))
+        return out, sup, offs
 
     def generate_radial(self, taper, w, out=None, stream=None):
         """Radial lines as a flat complex128 tensor [sum nrho] (asynchronous)."""

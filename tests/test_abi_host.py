@@ -95,6 +95,8 @@ def test_null_arguments(lib):
     assert lib.wkern_layout_desc(None, None, None) == 1
     assert lib.wkern_plan(None, None) == 1
     assert lib.wkern_generate(None, None, None, None, None) == 1
+    assert lib.wkern_generate_truncated(None, None, None, 0.01, None, 0, None, None, None) == 1
+    assert lib.wkern_generate_radial(None, None, None, None, None) == 1
     assert lib.wkern_grad(None, None, None, None, None, None, None) == 1
     assert lib.wkern_destroy(None) == 0
     for s in range(6):

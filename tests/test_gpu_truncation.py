@@ -1,0 +1,113 @@
+"""Truncation step of Algorithm 2 (section 3.1) on the GPU against the oracle:
+per plane the support is chosen from the radial line (last node at or above
+frac x the maximum amplitude), the layout is packed at device-computed
+offsets, and the cache is sampled from the spline through the full line.
+Supports are compared exactly; where the oracle's deciding node sits within
+1e-6 (relative) of the threshold a one-step difference is allowed and
+reported (both sides decide in FP64 but on values that differ by the
+contraction's rounding).  Caches: per-plane error <= the precision's gate."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hankel as H
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GATE = {"fp32": 1e-5, "bf16x6": 1e-6}
+
+
+def _near_tie(line, frac, s_gpu, s_ref, qos):
+    amp = np.abs(line)
+    thr = frac * amp.max()
+    # nodes whose decision differs between the two supports
+    lo = (min(s_gpu, s_ref) - 1) // 2 * qos
+    hi = (max(s_gpu, s_ref) - 1) // 2 * qos
+    cand = amp[max(0, lo - qos):hi + 1]
+    return np.min(np.abs(cand - thr)) <= 1e-6 * amp.max()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("frac", [0.01, 0.001])
+def test_truncated_paper_workload(precision, frac):
+    from paper_1904_08463_amd import Plan
+    base = W.paper()
+    s_max = base.max_support
+    sup_plan = np.full(base.n_planes, s_max, dtype=np.int32)
+    print(f"case paper truncated frac={frac} precision={precision}", flush=True)
+    plan = Plan(base.image_size, base.cellsize, base.n_radial, base.oversampling, sup_plan, s_max,
+                precision=precision)
+    taper = torch.from_numpy(base.taper).cuda()
+    w = torch.from_numpy(base.w).cuda()
+    out, sup, offs = plan.generate_truncated(taper, w, frac)
+    out, sup, offs = out.cpu().numpy(), sup.cpu().numpy(), offs.cpu().numpy()
+    assert offs[0] == 0 and np.array_equal(np.diff(offs), base.oversampling ** 2 * sup.astype(np.int64) ** 2)
+    # oracle supports for every plane (lines only), caches for a sample
+    geo = H.geometry(base.image_size, base.cellsize, base.n_radial, base.oversampling)
+    lines = H.radial_kernels(geo, base.taper, base.w, sup_plan)
+    qos = base.oversampling
+    ties = 0
+    for p, line in enumerate(lines):
+        s_ref = 2 * H.truncated_half_support(line, frac, base.oversampling, 1, (s_max - 1) // 2) + 1
+        if sup[p] != s_ref:
+            assert abs(int(sup[p]) - s_ref) == 2 and _near_tie(line, frac, sup[p], s_ref, qos), p
+            ties += 1
+    print(f"supports {sup.min()}..{sup.max()}, {ties} threshold ties", flush=True)
+    assert ties <= 2
+    planes = [0, 60, 128, 200, 255]
+    caches, sup_ref, _ = H.generate_truncated(base.image_size, base.cellsize, base.n_radial,
+                                              base.oversampling, base.taper, base.w, s_max,
+                                              frac=frac, planes=planes)
+    for j, p in enumerate(planes):
+        if sup[p] != sup_ref[j]:
+            continue
+        got = out[offs[p]:offs[p + 1]].reshape(caches[j].shape)
+        e = float(np.max(np.abs(got - caches[j])) / np.max(np.abs(caches[j])))
+        assert e <= GATE[precision], (p, e)
+    plan.close()
+
+
+def test_truncated_with_mirrors_and_small_cap():
+    """Mirrored planes take their source's support; planned supports act as
+    per-plane caps."""
+    from paper_1904_08463_amd import Plan
+    base = W.plain()
+    wl = W.plain(extra_w=[-v for v in base.w])
+    mir = W.mirror_table(wl.w, wl.support)
+    sup_plan = np.array([31, 21, 31, 15, 31, 31, 9, 31] * 2, dtype=np.int32)
+    plan = Plan(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, sup_plan, 31, mirror=mir)
+    taper = torch.from_numpy(wl.taper).cuda()
+    w = torch.from_numpy(wl.w).cuda()
+    out, sup, offs = plan.generate_truncated(taper, w, 0.01)
+    out, sup, offs = out.cpu().numpy(), sup.cpu().numpy(), offs.cpu().numpy()
+    assert np.all(sup <= sup_plan)
+    for p in range(wl.n_planes):
+        caches, s_ref, _ = H.generate_truncated(wl.image_size, wl.cellsize, wl.n_radial,
+                                                wl.oversampling, wl.taper, wl.w, int(sup_plan[p]),
+                                                frac=0.01, planes=[p])
+        assert sup[p] == s_ref[0], (p, sup[p], s_ref[0])
+        got = out[offs[p]:offs[p + 1]].reshape(caches[0].shape)
+        e = float(np.max(np.abs(got - caches[0])) / np.max(np.abs(caches[0])))
+        assert e <= 1e-5, (p, e)
+        if mir[p] >= 0:
+            q = mir[p]
+            assert sup[p] == sup[q]
+            assert np.array_equal(got, np.conj(out[offs[q]:offs[q + 1]].reshape(got.shape)))
+    plan.close()
+
+
+def test_truncated_rejects_bad_arguments():
+    from paper_1904_08463_amd import Plan
+    from paper_1904_08463_amd.wkern import WkernError
+    wl = W.plain()
+    plan = Plan.from_workload(wl)
+    taper = torch.from_numpy(wl.taper).cuda()
+    w = torch.from_numpy(wl.w).cuda()
+    for frac in (0.0, 1.0, -0.5, float("nan")):
+        with pytest.raises(WkernError):
+            plan.generate_truncated(taper, w, frac)
+    small = torch.empty(int(plan.offsets[-1]) - 1, dtype=torch.complex64, device="cuda")
+    with pytest.raises(WkernError):
+        plan.generate_truncated(taper, w, 0.01, out=small)
+    plan.close()

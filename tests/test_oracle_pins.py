@@ -342,3 +342,46 @@ def test_paper_sizing_statements():
     pf = g["padded_full_image"]
     assert pf["image_size"] * pf["oversampling"] == pf["padded"]
     assert round(pf["padded"] ** 2 * 16 / 1e9) == pf["gigabytes"]
+
+
+# ---------------------------------------------------------------------------
+# truncation (section 3.1, Algorithm 2)
+# ---------------------------------------------------------------------------
+def test_truncation_gaussian_closed_form():
+    """w = 0, Gaussian taper: K = 2 pi sig^2 exp(-2 pi^2 sig^2 rho^2) falls to 1%
+    of its peak at rho_1 = sqrt(ln 100 / (2 pi^2 sig^2)); the truncated
+    half-width is the first whole uv cell at or beyond it."""
+    sig = 0.004
+    wl = W.plain(n_radial=2048)
+    fn = W.gaussian_taper(sig)
+    tau = W.sample_taper(fn, 2048, wl.r_max)
+    geo = H.geometry(wl.image_size, wl.cellsize, 2048, 4)
+    _, sup, lines = H.generate_truncated(wl.image_size, wl.cellsize, 2048, 4, tau, [0.0], 63)
+    rho1 = math.sqrt(math.log(100.0) / (2 * math.pi ** 2 * sig ** 2))
+    k1 = rho1 / geo.drho
+    # the last node above 1% is floor(k1) (K is monotone here)
+    assert int(sup[0]) == 2 * math.ceil(math.floor(k1) / 4) + 1
+    assert 1 < sup[0] < 63
+
+
+def test_truncation_monotone_and_clamped():
+    wl = W.paper(n_planes=8, n_radial=1024)
+    prev = None
+    for frac in (0.1, 0.01, 0.001, 1e-6):
+        _, sup, _ = H.generate_truncated(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling,
+                                         wl.taper, wl.w, 63, frac=frac)
+        assert np.all(sup <= 63) and np.all(sup % 2 == 1)
+        if prev is not None:
+            assert np.all(sup >= prev)
+        prev = sup
+    assert np.all(prev == 63)  # a tiny fraction keeps the maximum support
+
+
+def test_truncated_cache_uses_full_line():
+    wl = W.plain()
+    caches, sup, lines = H.generate_truncated(wl.image_size, wl.cellsize, wl.n_radial,
+                                              wl.oversampling, wl.taper, wl.w[:3], 31)
+    for c, s, line in zip(caches, sup, lines):
+        assert c.shape == (4, 4, s, s)
+        assert len(line) == H.n_rho([31], 4)[0]
+        np.testing.assert_array_equal(c, H.resample(line, int(s), 4))
