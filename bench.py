@@ -14,7 +14,9 @@ same inputs and reported beside it.  One JSON line is printed.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -26,6 +28,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16x6": 2500.0, "fp32": 157.3}  # dense BF16 / FP32 matrix peaks
+# HBM bytes per k_resample launch from two counter runs (FETCH_SIZE, WRITE_SIZE),
+# valid only for the kernel sources they were taken with
+COUNTERS = os.path.join(ROOT, "profiles", "k_resample_batch_counters.txt")
+RESAMPLE_SOURCES = ("paper_1904_08463_amd/csrc/wkern_resample.hip",
+                    "paper_1904_08463_amd/csrc/wkern_radial.h",
+                    "paper_1904_08463_amd/csrc/wkern_internal.h")
 
 
 def _parse():
@@ -34,7 +43,7 @@ def _parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=16,
+    ap.add_argument("--cpu-stride", type=int, default=4,
                     help="oracle sample: every n-th plane in support order")
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-fft", action="store_true")
@@ -64,6 +73,45 @@ def _time_path(plan, taper, w, out, steps, warmup):
     stages, calls = plan.stage_times()
     plan.set_profiling(False)
     return wall, {k: v / max(calls, 1) for k, v in stages.items()}
+
+
+def resample_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in RESAMPLE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _measured_traffic():
+    """HBM bytes per k_resample launch (FETCH + WRITE, each scaled by what
+    the counter reads for a copy of known size), or None when the summary is
+    missing or the resample sources changed after the counters were taken."""
+    try:
+        with open(COUNTERS) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^(source_sha256|traffic_bytes_per_launch):\s*(\S+)", text, re.M))
+    if kv.get("source_sha256") != resample_source_digest() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def _contraction_roofline(plan, wl, stages, precision):
+    """MFMA roofline of the Hankel contraction: algorithmic 4 Nr Nrho FLOP per
+    computed plane (mirrored planes are not contracted); the split path
+    executes six BF16 products per algorithmic one."""
+    nrho = plan.nrho.astype(np.float64)
+    computed = np.ones(wl.n_planes, dtype=bool) if plan.mirror is None else plan.mirror < 0
+    flop = 4.0 * wl.n_radial * float(nrho[computed].sum())
+    executed = flop * (6.0 if precision == "bf16x6" else 1.0)
+    ms = stages["contraction"]
+    achieved = executed / (ms * 1e-3) / 1e12
+    peak = MFMA_PEAK_TFLOPS[precision]
+    return {"bound": "mfma", "kernel": "k_contract_*", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "algorithmic_flop": flop,
+            "executed_flop": executed, "ms": ms}
 
 
 def _sampled_error(plan, out, wl, planes):
@@ -194,7 +242,8 @@ def main():
     paths = {"bf16x6": {"kernels_per_s": value, "ms_per_step": ms,
                         "stage_ms": stages, "max_rel_err_sampled": err_bf16,
                         "pipeline_chunks": info["chunks"], "contraction_variant": info["variant"],
-                        "autotune_ms": info["variant_ms"]}}
+                        "autotune_ms": info["variant_ms"],
+                        "contraction_roofline": _contraction_roofline(plan, wl, stages, "bf16x6")}}
     plan.close()
     # every plane computed on its own (no use of K(-w) = conj K(w), section 4.1)
     plan_all = Plan.from_workload(wl, precision="bf16x6", use_mirror=False)
@@ -213,7 +262,8 @@ def main():
                          "ms_per_step": 1000.0 * wall32 / args.steps, "stage_ms": stages32,
                          "max_rel_err_sampled": err32, "pipeline_chunks": info32["chunks"],
                          "contraction_variant": info32["variant"],
-                         "autotune_ms": info32["variant_ms"]}
+                         "autotune_ms": info32["variant_ms"],
+                         "contraction_roofline": _contraction_roofline(plan32, wl, stages32, "fp32")}
         plan32.close()
 
     if not args.skip_fft:
@@ -238,7 +288,8 @@ def main():
                    "n_kernels": wl.n_planes, "output_bytes": out_bytes},
         "roofline": {"bound": "hbm", "kernel": "k_resample", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": _measured_traffic(), "ms": res_ms,
+                     "algorithmic_bytes": out_bytes},
         "paths": paths,
     }
     if not args.no_cpu_baseline:

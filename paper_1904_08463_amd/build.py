@@ -23,6 +23,7 @@ SOURCES = [
     ("wkern.cpp", False),
     ("wkern_kernels.hip", True),
     ("wkern_fft2d.hip", True),
+    ("wkern_resample.hip", True),
 ]
 LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
 
