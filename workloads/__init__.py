@@ -245,6 +245,65 @@ def random_small(seed: int, n_planes: int = 5, n_radial: int = 96, os_: int = 3,
         notes="randomised property-test workload")
 
 
+# --------------------------------------------------------------------------
+# Visibility w coordinates: the input of the w-plane partition
+# --------------------------------------------------------------------------
+C_LIGHT = 299792458.0
+
+
+def y_array(n_per_arm: int = 9, arm_m: float = 1900.0, az0_deg: float = 5.0,
+            seed: int = SEED) -> np.ndarray:
+    """East-north-up positions (m) of a Y-shaped array: three arms at azimuths
+    az0, az0 + 120, az0 + 240 deg with antennas at d_k = arm (k / n)^1.7,
+    k = 1..n, plus a seeded 1 m jitter."""
+    rng = np.random.default_rng(seed)
+    pos = []
+    for arm in range(3):
+        az = np.deg2rad(az0_deg + 120.0 * arm)
+        for k in range(1, n_per_arm + 1):
+            d = arm_m * (k / n_per_arm) ** 1.7
+            pos.append([d * np.sin(az), d * np.cos(az), 0.0])
+    return np.asarray(pos) + rng.normal(0.0, 1.0, (3 * n_per_arm, 3)) * [1.0, 1.0, 0.1]
+
+
+def uvw_tracks(enu: np.ndarray, freq_hz: float, dec_deg: float, lat_deg: float,
+               n_times: int, ha_span_h: float = 12.0):
+    """(u, v, w) in wavelengths of every baseline at n_times hour angles evenly
+    spread over +-ha_span/2; records time-major (all baselines of a dump, then
+    the next dump), as a measurement set holds them."""
+    lat, dec = np.deg2rad(lat_deg), np.deg2rad(dec_deg)
+    e, n_, u_ = enu[:, 0], enu[:, 1], enu[:, 2]
+    xyz = np.stack([-np.sin(lat) * n_ + np.cos(lat) * u_, e,
+                    np.cos(lat) * n_ + np.sin(lat) * u_], axis=1)
+    a, b = np.triu_indices(enu.shape[0], 1)
+    bl = (xyz[b] - xyz[a]) * (freq_hz / C_LIGHT)
+    ha = np.deg2rad(15.0 * ha_span_h * ((np.arange(n_times) + 0.5) / n_times - 0.5))
+    sh, ch = np.sin(ha)[:, None], np.cos(ha)[:, None]
+    X, Y, Z = bl[:, 0][None, :], bl[:, 1][None, :], bl[:, 2][None, :]
+    u = sh * X + ch * Y
+    v = -np.sin(dec) * ch * X + np.sin(dec) * sh * Y + np.cos(dec) * Z
+    w = np.cos(dec) * ch * X - np.cos(dec) * sh * Y + np.sin(dec) * Z
+    return u.reshape(-1), v.reshape(-1), w.reshape(-1)
+
+
+def vla_c_74mhz_w(n_times: int = 1440) -> np.ndarray:
+    """w of the partition workload shaped like the paper's simulation (section
+    5): a 27-antenna Y array of C-configuration extent at 74 MHz, pointing at
+    dec +47.34 deg from latitude 34.08 deg, 351 baselines x 1440 dumps over
+    +-6 h = 505440 records."""
+    _, _, w = uvw_tracks(y_array(), 74e6, 47.339, 34.079, n_times)
+    return w
+
+
+def multichannel_w(w: np.ndarray, n_chan: int, f_lo: float = 1.0, f_hi: float = 1.5) -> np.ndarray:
+    """The same records over n_chan channels, w scaled by nu_c / nu_lo,
+    nu_c evenly spaced on [f_lo, f_hi]; channel-major."""
+    if n_chan == 1:
+        return np.asarray(w, dtype=np.float64).copy()
+    nu = f_lo + (f_hi - f_lo) * np.arange(n_chan) / (n_chan - 1)
+    return (np.asarray(w, dtype=np.float64)[None, :] * (nu / f_lo)[:, None]).reshape(-1)
+
+
 WORKLOADS = {
     "plain": plain,
     "paper": paper,
