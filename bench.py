@@ -159,6 +159,32 @@ def _fft_paths(wl, taper, w, out, steps):
     return res
 
 
+def _wpartition_paths(steps):
+    """w-plane partition (sort by |w|, equal-size planes, mean |w|): the
+    paper-shaped record set (505440 records, 128 planes) and the same records
+    over 33 channels (16.7 M records, 256 planes)."""
+    import torch
+    import workloads as W
+    from paper_1904_08463_amd import wpartition, wpartition_workspace
+    base = W.vla_c_74mhz_w()
+    res = {}
+    for name, w, m in (("records_505440_planes_128", base, 128),
+                       ("records_16679520_planes_256", W.multichannel_w(base, 33), 256)):
+        wd = torch.from_numpy(w).cuda()
+        ws = torch.empty(wpartition_workspace(w.size), dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            wpartition(wd, m, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            wpartition(wd, m, workspace=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"records_per_s": w.size / dt, "ms": 1000.0 * dt, "n_records": int(w.size),
+                     "n_planes": m, "steps": steps}
+    return res
+
+
 def _profile_pass(wl):
     """Kernels for a hardware-counter run: two generate calls of the split path
     and a plain 2 GiB device-to-device copy of known size."""
@@ -268,6 +294,7 @@ def main():
 
     if not args.skip_fft:
         paths.update(_fft_paths(wl, taper, w, out, args.fft_steps))
+    paths["wpartition"] = _wpartition_paths(args.steps)
 
     line = {
         "metric": "w-kernels/sec at <=1e-6 rel err (split-BF16 Hankel; FP32 Hankel beside it)",

@@ -49,6 +49,7 @@
 #define WKERN_H
 
 #include <stdint.h>
+#include <stddef.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -258,6 +259,49 @@ wkern_status wkern_fft2d_generate(wkern_fft2d_t plan, const float* taper, const 
 
 /* Release the comparison plan (synchronises its device first). */
 wkern_status wkern_fft2d_destroy(wkern_fft2d_t plan);
+
+/* -------------------------------------------------------------------------
+ * w-plane partition of visibility records: the first three steps of
+ * Algorithm 2 (sort by increasing absolute w-term, divide into M equally
+ * sized w-planes, average or median w-term per plane; Algorithm 1 is the
+ * same with signed w).  The plane w-terms come back in device memory, ready
+ * to be passed as `w` to wkern_generate / wkern_generate_truncated.
+ *
+ * Conventions: plane m holds the sorted positions
+ * [floor(m n / M), floor((m + 1) n / M)); records with equal keys keep their
+ * input order (stable); -0.0 sorts as +0.0 and every NaN after all numbers.
+ * With absolute = 1 the key and the statistic are |w| (a record with w < 0
+ * is gridded with the conjugate kernel, section 4.1); with absolute = 0 they
+ * are w.  The mean sums in a fixed order (bit-reproducible); the median of
+ * an even count is the mean of the two middle values.
+ * ------------------------------------------------------------------------- */
+typedef enum { WKERN_WSTAT_MEAN = 0, WKERN_WSTAT_MEDIAN = 1 } wkern_wstat;
+
+/* Device workspace wkern_wpartition needs for n_records records on the
+ * current device.  Errors: INVALID_ARG, UNSUPPORTED (n_records > 2^31 - 1),
+ * DEVICE. */
+wkern_status wkern_wpartition_workspace(int64_t n_records, size_t* bytes);
+
+/* w:           device double [n_records], w-terms in wavelengths.
+ * n_planes:    M, 1 <= M <= n_records.
+ * absolute:    1: Algorithm 2 (|w|); 0: Algorithm 1 (signed w).
+ * stat:        WKERN_WSTAT_MEAN or WKERN_WSTAT_MEDIAN.
+ * workspace:   caller-owned device memory of at least
+ *              wkern_wpartition_workspace(n_records) bytes, 256-byte aligned;
+ *              its contents are scratch.
+ * order:       device int32 [n_records] (written): record indices in sorted
+ *              order; plane m's records are order[plane_start[m] ..
+ *              plane_start[m + 1] - 1].
+ * plane_start: device int64 [M + 1] (written).
+ * w_plane:     device double [M] (written): the plane w-terms (|w| when
+ *              absolute = 1).
+ * Asynchronous on `stream`; allocates nothing.  Errors: INVALID_ARG (NULL
+ * pointer, M out of range, short or misaligned workspace), UNSUPPORTED
+ * (n_records > 2^31 - 1), DEVICE. */
+wkern_status wkern_wpartition(const double* w, int64_t n_records, int32_t n_planes,
+                              int32_t absolute, int32_t stat, void* workspace,
+                              size_t workspace_bytes, int32_t* order, int64_t* plane_start,
+                              double* w_plane, void* stream);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,7 @@ SOURCES = [
     ("wkern_kernels.hip", True),
     ("wkern_fft2d.hip", True),
     ("wkern_resample.hip", True),
+    ("wkern_wpartition.hip", True),
 ]
 LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
 

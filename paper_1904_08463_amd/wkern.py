@@ -36,6 +36,7 @@ EXPORTS = (
     "wkern_set_chunks", "wkern_set_graph", "wkern_destroy",
     "wkern_strerror", "wkern_last_error",
     "wkern_fft2d_plan", "wkern_fft2d_generate", "wkern_fft2d_destroy",
+    "wkern_wpartition_workspace", "wkern_wpartition",
 )
 
 
@@ -118,6 +119,11 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_fft2d_generate.argtypes = [vp, vp, vp, vp, vp]
     lib.wkern_fft2d_destroy.restype = ctypes.c_int
     lib.wkern_fft2d_destroy.argtypes = [vp]
+    lib.wkern_wpartition_workspace.restype = ctypes.c_int
+    lib.wkern_wpartition_workspace.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.wkern_wpartition.restype = ctypes.c_int
+    lib.wkern_wpartition.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, vp, ctypes.c_size_t, vp, vp, vp, vp]
     if lib.wkern_abi_version() != ABI_VERSION:
         raise WkernError(5, f"library ABI {lib.wkern_abi_version()}, binding {ABI_VERSION}")
     _lib = lib
@@ -384,3 +390,39 @@ class FFT2DPlan:
             self.close()
         except Exception:
             pass
+
+
+WSTAT = {"mean": 0, "median": 1}
+
+
+def wpartition_workspace(n_records: int, device: int = 0) -> int:
+    """Device workspace bytes wpartition needs for n_records records."""
+    import torch
+    lib = load_library()
+    n = ctypes.c_size_t()
+    with torch.cuda.device(device):
+        _check(lib.wkern_wpartition_workspace(int(n_records), ctypes.byref(n)))
+    return int(n.value)
+
+
+def wpartition(w, n_planes: int, absolute: bool = True, stat: str = "mean", workspace=None,
+               stream=None):
+    """w-plane partition of visibility records (asynchronous): returns device
+    tensors (order int32 [n], plane_start int64 [M + 1], w_plane float64 [M]).
+    w: device float64 [n]."""
+    import torch
+    if w.dtype != torch.float64 or not w.is_cuda or w.dim() != 1:
+        raise ValueError("w must be a 1-D float64 device tensor")
+    w = w.contiguous()
+    n = w.numel()
+    dev = w.device
+    if workspace is None:
+        workspace = torch.empty(wpartition_workspace(n, dev.index or 0), dtype=torch.uint8,
+                                device=dev)
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    start = torch.empty(n_planes + 1, dtype=torch.int64, device=dev)
+    w_plane = torch.empty(n_planes, dtype=torch.float64, device=dev)
+    _check(load_library().wkern_wpartition(
+        _ptr(w), n, int(n_planes), 1 if absolute else 0, WSTAT[stat], _ptr(workspace),
+        workspace.numel(), _ptr(order), _ptr(start), _ptr(w_plane), _stream_handle(stream)))
+    return order, start, w_plane

@@ -97,6 +97,10 @@ def test_null_arguments(lib):
     assert lib.wkern_generate(None, None, None, None, None) == 1
     assert lib.wkern_generate_truncated(None, None, None, 0.01, None, 0, None, None, None) == 1
     assert lib.wkern_generate_radial(None, None, None, None, None) == 1
+    assert lib.wkern_wpartition(None, 10, 2, 1, 0, None, 0, None, None, None, None) == 1
+    n = ctypes.c_size_t()
+    assert lib.wkern_wpartition_workspace(0, ctypes.byref(n)) == 1
+    assert lib.wkern_wpartition_workspace(1 << 31, ctypes.byref(n)) == 4
     assert lib.wkern_grad(None, None, None, None, None, None, None) == 1
     assert lib.wkern_destroy(None) == 0
     for s in range(6):
