@@ -18,6 +18,9 @@ Wide-field Imaging"):
   screen on a Cartesian workspace, zero padded by the oversampling factor,
   2D DFT, kernel cache extraction.  This is the twin the Hankel path is
   compared against inside the circular region (section 4.4).
+* ``projslice`` -- the paper's own Hankel engine (section 4.3.1): 1D
+  projection of the workspace screen, zero-padded 1D FFT, then the same
+  interpolation as ``hankel``.
 * ``wpartition`` -- the w-plane partition that opens Algorithms 1 and 2:
   sort by (absolute) w, equal-size planes, average or median w per plane.
 * ``adjoint``  -- the exact gradient of a real loss of the kernel cache with
@@ -27,4 +30,4 @@ Wide-field Imaging"):
 Parity status of each function is listed in its docstring.  Readings of the
 paper where it is silent or ambiguous are listed in ``hankel``'s header.
 """
-from . import hankel, fft2d, adjoint, wpartition  # noqa: F401
+from . import hankel, fft2d, adjoint, projslice, wpartition  # noqa: F401

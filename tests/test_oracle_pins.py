@@ -19,6 +19,7 @@ from scipy.special import j1
 
 import workloads as W
 from oracle import adjoint as A
+from oracle import projslice as PS
 from oracle import fft2d as F
 from oracle import hankel as H
 
@@ -385,3 +386,63 @@ def test_truncated_cache_uses_full_line():
         assert c.shape == (4, 4, s, s)
         assert len(line) == H.n_rho([31], 4)[0]
         np.testing.assert_array_equal(c, H.resample(line, int(s), 4))
+
+
+# ---------------------------------------------------------------------------
+# Projection-slice engine (section 4.3.1, Algorithm 2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("w", [0.0, 300.0, 937.5])
+@pytest.mark.parametrize("os_,q", [(4, 1), (3, 1), (2, 2)])
+def test_projslice_line_is_the_2d_transform_axis(w, os_, q):
+    """Discrete projection-slice theorem: the padded 1D transform of the
+    projection equals the v = 0 row of the padded 2D transform (oracle.fft2d)
+    of the same workspace, sample for sample."""
+    wl = W.plain()
+    fov = wl.image_size * wl.cellsize
+    n_ws = 64
+    line = PS.line(wl.taper_fn, w, 31, os_, fov, q, n_ws)
+    spec = F.padded_transform(F.workspace_screen(wl.taper_fn, w, n_ws, fov), q * os_, fov)
+    c = spec.shape[0] // 2
+    ref = spec[c, c:c + line.shape[0]]
+    assert np.max(np.abs(line - ref)) / np.max(np.abs(ref)) < 1e-12
+
+
+def test_projslice_brute_force_tiny():
+    wl = W.plain()
+    fov = wl.image_size * wl.cellsize
+    scr = F.workspace_screen(wl.taper_fn, 700.0, 8, fov)
+    line = PS.line(wl.taper_fn, 700.0, 5, 3, fov, 1, 8)
+    ref = PS.brute_line(scr, fov, 3, line.shape[0])
+    assert np.max(np.abs(line - ref)) / np.max(np.abs(ref)) < 1e-13
+
+
+def test_projslice_gaussian_closed_form():
+    """w = 0 and a Gaussian taper far inside the disc: the line is the
+    Gaussian's transform 2 pi sig^2 exp(-2 pi^2 sig^2 rho^2)."""
+    sig, fov = 0.004, 0.1
+    line = PS.line(W.gaussian_taper(sig), 0.0, 31, 4, fov, 1, 256)
+    rho = np.arange(line.shape[0]) / (4 * fov)
+    ref = 2 * math.pi * sig * sig * np.exp(-2 * math.pi ** 2 * sig * sig * rho ** 2)
+    assert np.max(np.abs(line - ref)) / ref[0] < 1e-12
+
+
+def test_projslice_agrees_with_matrix_form_on_smooth_edge():
+    """Both transforms approximate the same continuous HT: with a taper that
+    vanishes smoothly at r_max they agree to the quadrature errors."""
+    r_max, fov = 0.05, 0.1
+    base = W.gaussian_taper(0.02)
+    fn = lambda r: base(r) * np.clip(1 - (np.asarray(r) / r_max) ** 2, 0, None) ** 2  # noqa: E731
+    geo = H.geometry(128, 7.8125e-4, 4096, 4)
+    tau = fn(geo.r)
+    for w in (62.5, 562.5, 937.5):
+        k_h = H.radial_kernels(geo, tau, [w], [31])[0]
+        k_p = PS.line(fn, w, 31, 4, fov, 1, 128)
+        assert np.max(np.abs(k_h - k_p)) / np.max(np.abs(k_h)) < 2e-6
+
+
+@pytest.mark.parametrize("s,os_,q,min_w,n", [(7, 8, 1, None, 8), (9, 8, 1, None, 16),
+                                             (255, 8, 1, None, 256), (31, 1, 1, None, 64),
+                                             (1, 1, 1, None, 8), (7, 8, 1, 255, 256),
+                                             (31, 4, 2, None, 32)])
+def test_projslice_workspace_size(s, os_, q, min_w, n):
+    assert PS.workspace_size(s, os_, q, min_w) == n
