@@ -183,6 +183,26 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
                         const void* grad_out, float* grad_taper, double* grad_w,
                         void* stream);
 
+/* Engine of the radial-line step (steps 1-2).
+ * WKERN_ENGINE_MATRIX (default): the discrete HT matrix times the sampled
+ *   screen on the matrix cores (section 4.3), in the plan's precision.
+ * WKERN_ENGINE_PROJECTION_SLICE: the paper's own route (section 4.3.1,
+ *   Algorithm 2): the IConv-kernel on an N x N image workspace (pixel
+ *   l = (x - N/2) FOV/N, zero outside the open disc r < r_max, the taper
+ *   linear in r between its samples), projected onto one axis and
+ *   transformed with zero padding by q os, in FP64.  N is the power of two at
+ *   or above max(S_p, 2) (workspace_mode 1, per plane) or max(max_support, 2)
+ *   (workspace_mode 0), doubled until q os N / 2 >= nrho; q os N must not
+ *   exceed 8192.  It is a different discretisation of the same transform:
+ *   its line equals, sample for sample, the v = 0 row of the 2D FFT of that
+ *   workspace, not the matrix form's line.
+ * Both engines feed the same spline and resample.  wkern_grad supports the
+ * matrix engine only.  Synchronises the plan's device; the captured graph is
+ * rebuilt on the next call.  Errors: INVALID_ARG, UNSUPPORTED,
+ * OUT_OF_MEMORY, DEVICE. */
+typedef enum { WKERN_ENGINE_MATRIX = 0, WKERN_ENGINE_PROJECTION_SLICE = 1 } wkern_engine;
+wkern_status wkern_set_engine(wkern_plan_t plan, int32_t engine, int32_t workspace_mode);
+
 /* Stage timing of wkern_generate with HIP events recorded on the call's own
  * stream around each stage (0 screen, 1 contraction, 2 spline, 3 resample);
  * recording adds no synchronisation.  enable != 0 clears and starts

@@ -16,8 +16,9 @@ interpolation and the transform's sign and scale):
 
 PS1 The workspace of a plane is the power of two at or above its full width
     S_p (section 4.2, workspace undersampling), or at or above the maximum
-    support for every plane (the fixed setting of sections 5 and 6.3); it is
-    doubled until the padded transform reaches the line's last node,
+    support for every plane (the fixed setting of sections 5 and 6.3), and
+    at least 2 (a centred workspace needs an even width); it is doubled
+    until the padded transform reaches the line's last node,
     q os N_ws / 2 >= nrho = q os h + 4.
 PS2 Projection onto the l axis: p(l) = sum over m of s(l, m) dm; transform
     K(rho) = sum over l of p(l) exp(-j 2 pi rho l) dl, zero padded by q os so
@@ -45,7 +46,7 @@ TWO_PI = 2.0 * math.pi
 def workspace_size(support: int, oversampling: int, radial_refine: int = 1,
                    min_width: int | None = None) -> int:
     """N_ws of a plane (PS1)."""
-    n = F.next_pow2(max(support, min_width or 0))
+    n = F.next_pow2(max(support, min_width or 0, 2))
     nrho = radial_refine * oversampling * ((support - 1) // 2) + 4
     while radial_refine * oversampling * n // 2 < nrho:
         n *= 2

@@ -189,6 +189,13 @@ struct wkern_plan_s {
   GradScratch grad{};
   bool gradReady = false;
 
+  // radial-line engine: 0 matrix form (HT matrix on the matrix cores),
+  // 1 projection-slice; the latter writes one K-chunk, so its spline and
+  // line views carry nkc = 1
+  int engine = WKERN_ENGINE_MATRIX;
+  int psMode = 0;
+  PsTables ps{};
+
   // stage profiling
   bool profiling = false;
   int profiledCalls = 0;
@@ -646,6 +653,30 @@ static wkern_status check_gen_args(wkern_plan_t plan, const void* taper, const v
   return WKERN_OK;
 }
 
+// The plan's tables as the spline and line-output kernels see them: the
+// projection-slice engine leaves a single K-chunk.
+static DevPlan lines_view(const wkern_plan_s* plan) {
+  DevPlan v = plan->dp;
+  if (plan->engine != WKERN_ENGINE_MATRIX) v.nkc = 1;
+  return v;
+}
+
+// Radial lines of every computed plane with the selected engine (no
+// profiling records): K-chunk partial sums in dp.part.
+static wkern_status enqueue_lines(wkern_plan_t plan, const float* taper, const double* w,
+                                  hipStream_t st) {
+  const DevPlan& g = plan->dp;
+  if (plan->engine == WKERN_ENGINE_MATRIX) {
+    const int v = plan->variant;
+    WK_HIP(launch_screen(g, 0, g.P, taper, w, st), "screen launch");
+    WK_HIP(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
+           "contraction launch");
+  } else {
+    WK_HIP(launch_ps_lines(g, plan->ps, 0, g.P, taper, w, st), "projection-slice launch");
+  }
+  return WKERN_OK;
+}
+
 // Screen, contraction and spline of pipeline chunk c, then its resample.
 static wkern_status enqueue_chunk(wkern_plan_t plan, int c, const float* taper, const double* w,
                                   void* out, hipStream_t compute, hipStream_t store,
@@ -656,14 +687,19 @@ static wkern_status enqueue_chunk(wkern_plan_t plan, int c, const float* taper, 
   const int t0 = plan->chunkT[v][c], t1 = plan->chunkT[v][c + 1];
   StageRecord* r;
   wkern_status s;
-  if ((s = plan->record_begin(0, compute, &r)) != WKERN_OK) return s;
-  WK_HIP(launch_screen(g, j0, j1, taper, w, compute), "screen launch");
-  if ((s = record_end(r, compute)) != WKERN_OK) return s;
-  if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;
-  WK_HIP(launch_contract(g, v, plan->d_tiles[v] + t0, t1 - t0, compute), "contraction launch");
+  if (plan->engine == WKERN_ENGINE_MATRIX) {
+    if ((s = plan->record_begin(0, compute, &r)) != WKERN_OK) return s;
+    WK_HIP(launch_screen(g, j0, j1, taper, w, compute), "screen launch");
+    if ((s = record_end(r, compute)) != WKERN_OK) return s;
+    if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;
+    WK_HIP(launch_contract(g, v, plan->d_tiles[v] + t0, t1 - t0, compute), "contraction launch");
+  } else {
+    if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;
+    WK_HIP(launch_ps_lines(g, plan->ps, j0, j1, taper, w, compute), "projection-slice launch");
+  }
   if ((s = record_end(r, compute)) != WKERN_OK) return s;
   if ((s = plan->record_begin(2, compute, &r)) != WKERN_OK) return s;
-  WK_HIP(launch_spline(g, j0, j1, compute), "spline launch");
+  WK_HIP(launch_spline(lines_view(plan), j0, j1, compute), "spline launch");
   if ((s = record_end(r, compute)) != WKERN_OK) return s;
   if (handoff) {
     WK_HIP(hipEventRecord(handoff, compute), "hipEventRecord");
@@ -791,11 +827,9 @@ wkern_status wkern_generate_truncated(wkern_plan_t plan, const float* taper, con
     plan->truncReady = true;
   }
   hipStream_t st = (hipStream_t)stream;
-  const int v = plan->variant;
-  WK_HIP(launch_screen(g, 0, g.P, taper, w, st), "screen launch");
-  WK_HIP(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
-         "contraction launch");
-  WK_HIP(launch_resample_truncated(g, plan->trunc, frac, support_out, offsets_out, out, st),
+  if ((s = enqueue_lines(plan, taper, w, st)) != WKERN_OK) return s;
+  WK_HIP(launch_resample_truncated(lines_view(plan), plan->trunc, frac, support_out, offsets_out,
+                                   out, st),
          "truncated resample launch");
   return WKERN_OK;
 }
@@ -840,6 +874,57 @@ wkern_status wkern_plan_info(wkern_plan_t plan, int32_t* variant, int32_t* n_var
   return WKERN_OK;
 }
 
+// Workspace width of the projection-slice engine for one plane: the power of
+// two at or above max(S, min_width, 2), doubled until the padded transform
+// reaches the line's last node.
+static int ps_width(int S, int minWidth, int pad, int nrho) {
+  int n = 2;
+  while (n < S || n < minWidth) n *= 2;
+  while (pad * n / 2 < nrho) n *= 2;
+  return n;
+}
+
+wkern_status wkern_set_engine(wkern_plan_t plan, int32_t engine, int32_t workspace_mode) {
+  clear_error();
+  if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
+  if (engine != WKERN_ENGINE_MATRIX && engine != WKERN_ENGINE_PROJECTION_SLICE)
+    return fail(WKERN_ERR_INVALID_ARG, "engine %d unknown", engine);
+  if (workspace_mode != 0 && workspace_mode != 1)
+    return fail(WKERN_ERR_INVALID_ARG, "workspace_mode %d not 0 or 1", workspace_mode);
+  DeviceGuard guard(plan->desc.device);
+  WK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  plan->graphValid = false;
+  if (engine == WKERN_ENGINE_MATRIX) {
+    plan->engine = engine;
+    return WKERN_OK;
+  }
+  const DevPlan& g = plan->dp;
+  const int pad = g.q * g.os;
+  const int minWidth = workspace_mode == 0 ? plan->desc.max_support : 0;
+  std::vector<int32_t> n(g.P);
+  int maxN = 2;
+  for (int j = 0; j < g.P; ++j) {
+    n[j] = ps_width(plan->support[plan->perm[j]], minWidth, pad, plan->nrhoSorted[j]);
+    maxN = std::max(maxN, n[j]);
+  }
+  const long long lmax = (long long)pad * maxN;
+  if (lmax > kPsMaxL)
+    return fail(WKERN_ERR_UNSUPPORTED, "padded transform %lld above %d", lmax, kPsMaxL);
+  std::vector<double> cosTab((size_t)lmax);
+  for (long long m = 0; m < lmax; ++m) cosTab[m] = std::cos(2.0 * M_PI * (double)m / (double)lmax);
+  plan->release(plan->ps.n);
+  plan->release(plan->ps.cosTab);
+  wkern_status s;
+  if ((s = plan->upload(&plan->ps.n, n, "projection-slice table")) != WKERN_OK) return s;
+  if ((s = plan->upload(&plan->ps.cosTab, cosTab, "projection-slice table")) != WKERN_OK) return s;
+  plan->ps.Lmax = (int)lmax;
+  plan->ps.maxN = maxN;
+  plan->ps.fov = (double)plan->desc.image_size * plan->desc.cellsize;
+  plan->engine = engine;
+  plan->psMode = workspace_mode;
+  return WKERN_OK;
+}
+
 wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant) {
   clear_error();
   if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
@@ -873,12 +958,8 @@ wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const 
   if (s != WKERN_OK) return s;
   DeviceGuard guard(plan->desc.device);
   hipStream_t st = (hipStream_t)stream;
-  const DevPlan& g = plan->dp;
-  const int v = plan->variant;
-  WK_HIP(launch_screen(g, 0, g.P, taper, w, st), "screen launch");
-  WK_HIP(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
-         "contraction launch");
-  WK_HIP(launch_lines_out(g, lines, st), "lines launch");
+  if ((s = enqueue_lines(plan, taper, w, st)) != WKERN_OK) return s;
+  WK_HIP(launch_lines_out(lines_view(plan), lines, st), "lines launch");
   return WKERN_OK;
 }
 
@@ -890,6 +971,8 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
   if (!grad_taper || !grad_w) return fail(WKERN_ERR_INVALID_ARG, "gradient output is NULL");
   if (plan->desc.oversampling > 32)
     return fail(WKERN_ERR_UNSUPPORTED, "gradient needs oversampling <= 32");
+  if (plan->engine != WKERN_ENGINE_MATRIX)
+    return fail(WKERN_ERR_UNSUPPORTED, "the adjoint covers the matrix-form engine only");
   DeviceGuard guard(plan->desc.device);
   const DevPlan& g = plan->dp;
   if (!plan->gradReady) {

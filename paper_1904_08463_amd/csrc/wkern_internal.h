@@ -155,4 +155,19 @@ hipError_t launch_resample_truncated(const DevPlan& p, const TruncScratch& ts, d
 hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStream_t s);
 hipError_t launch_lines_out(const DevPlan& p, void* lines, hipStream_t s);
 
+// Tables of the projection-slice engine (built when the engine is selected).
+struct PsTables {
+  int32_t* n;       // [P] workspace width N_ws of sorted plane j (a power of two)
+  double* cosTab;   // [Lmax] cos(2 pi m / Lmax), Lmax = q os max N_ws
+  int Lmax;
+  int maxN;
+  double fov;       // image_size * cellsize
+};
+// Largest padded transform length the engine's LDS tables hold.
+constexpr int kPsMaxL = 8192;
+// Radial lines of sorted planes [j0, j1) by projection and padded transform,
+// written to K-chunk 0 of the partial-sum buffer.
+hipError_t launch_ps_lines(const DevPlan& p, const PsTables& t, int j0, int j1,
+                           const float* taper, const double* w, hipStream_t s);
+
 }  // namespace wkern

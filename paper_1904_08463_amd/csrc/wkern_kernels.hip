@@ -1200,6 +1200,107 @@ __global__ __launch_bounds__(256) void k_grad_w(int Nr, int NrPad,
   if (threadIdx.x == 0) gw[perm[j]] = red[0];
 }
 
+// --------------------------------------------------------------------------
+// Projection-slice engine (section 4.3.1, Algorithm 2): the radial line of a
+// plane from its IConv-kernel sampled on an N x N workspace (pixel
+// l = (x - N/2) FOV/N, zero outside the open disc r < r_max, taper linear
+// in r between its midpoint samples), projected onto the l axis and
+// transformed with zero padding by q os:
+//   p(l_i) = dl sum_j s(l_i, m_j),  K(rho_k) = dl sum_i p(l_i) e^{-j 2 pi rho_k l_i}.
+// The sampled screen is even in both axes (the row and column at -N/2 lie
+// outside the disc), so with c = N/2 and offsets i, j in [0, c):
+//   p_i = dl (s(i, 0) + 2 sum_{j>0} s(i, j)),
+//   K_k = dl (p_0 + 2 sum_{i>0} p_i cos(2 pi k i / (q os N))).
+// Inside the disc iff i^2 + j^2 < c^2 (exact in integers).  FP64 throughout;
+// one workgroup per sorted plane; the cosine table comes from the plan,
+// sampled at stride Lmax / L for this plane's L = q os N.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double taper_at(double r, double dr, int Nr,
+                                           const float* __restrict__ taper) {
+  const double t = r / dr - 0.5;
+  if (t <= 0.0) return (double)taper[0];
+  const int i0 = (int)t;
+  if (i0 >= Nr - 1) return (double)taper[Nr - 1];
+  const double a = (double)taper[i0];
+  return a + (t - (double)i0) * ((double)taper[i0 + 1] - a);
+}
+
+constexpr int kPsThreads = 256;
+
+__global__ __launch_bounds__(kPsThreads) void k_ps_lines(
+    int j0, int Nr, double dr, double fov, int pad, int Lmax, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ psN, const int32_t* __restrict__ nrhoSorted,
+    const int32_t* __restrict__ lineOffSorted, const double* __restrict__ cosTab,
+    const float* __restrict__ taper, const double* __restrict__ w, double* __restrict__ part) {
+  extern __shared__ double ps_smem[];
+  const int j = j0 + blockIdx.x;
+  const int N = psN[j];
+  const int c = N / 2;
+  const int L = pad * N;
+  const int stride = Lmax / L;
+  // groups of threads sharing one offset i split the sum over j
+  const int G = c >= kPsThreads ? 1 : kPsThreads / c;
+  const int span = c >= kPsThreads ? kPsThreads : c;  // offsets per pass
+  double* cosL = ps_smem;                   // [L]
+  double2* proj = (double2*)(ps_smem + L);  // [c]
+  double2* partial = proj + c;              // [G][span]
+  const int tid = threadIdx.x;
+  for (int m = tid; m < L; m += kPsThreads) cosL[m] = cosTab[(size_t)m * stride];
+
+  const double dl = fov / (double)N;
+  const double wv = w[perm[j]];
+  const int lane = tid % span;
+  const int g = tid / span;
+  for (int base = 0; base < c; base += span) {
+    const int i = base + lane;
+    if (g < G) {
+      double re = 0.0, im = 0.0;
+      for (int jj = g; jj < c; jj += G) {
+        const int d2 = i * i + jj * jj;
+        if (d2 >= c * c) break;  // d2 grows with jj
+        const double r2 = (double)d2 * dl * dl;
+        const double phi = r2 / (1.0 + sqrt(1.0 - r2));
+        double t = wv * phi;
+        t -= rint(t);
+        double sn, cs;
+        sincospi(2.0 * t, &sn, &cs);
+        const double tau = taper_at(sqrt(r2), dr, Nr, taper);
+        const double wt = jj == 0 ? 1.0 : 2.0;
+        re += wt * tau * cs;
+        im += wt * tau * sn;
+      }
+      partial[g * span + lane] = make_double2(re, im);
+    }
+    __syncthreads();
+    if (tid < span) {
+      double re = 0.0, im = 0.0;
+      for (int gg = 0; gg < G; ++gg) {
+        re += partial[gg * span + tid].x;
+        im += partial[gg * span + tid].y;
+      }
+      proj[base + tid] = make_double2(re * dl, im * dl);
+    }
+    __syncthreads();
+  }
+
+  const int n = nrhoSorted[j];
+  double* dst = part + (size_t)lineOffSorted[j] * 2;
+  for (int k = tid; k < n; k += kPsThreads) {
+    double re = 0.0, im = 0.0;
+    int m = 0;  // k i mod L
+    for (int i = 1; i < c; ++i) {
+      m += k;
+      if (m >= L) m -= L;
+      const double cv = cosL[m];
+      re += proj[i].x * cv;
+      im += proj[i].y * cv;
+    }
+    dst[2 * k] = dl * (proj[0].x + 2.0 * re);
+    dst[2 * k + 1] = dl * (proj[0].y + 2.0 * im);
+  }
+}
+
+
 }  // namespace
 
 // ------------------------------ launchers ---------------------------------
@@ -1346,6 +1447,26 @@ hipError_t prepare_kernels(const DevPlan& p) {
   }
   return hipSuccess;
 }
+
+hipError_t launch_ps_lines(const DevPlan& p, const PsTables& t, int j0, int j1,
+                           const float* taper, const double* w, hipStream_t s) {
+  if (j1 <= j0) return hipSuccess;
+  const int c = t.maxN / 2;
+  const int span = c >= kPsThreads ? kPsThreads : c;
+  const int G = c >= kPsThreads ? 1 : kPsThreads / c;
+  const size_t shm = (size_t)t.Lmax * sizeof(double) + (size_t)c * sizeof(double2) +
+                     (size_t)G * span * sizeof(double2);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ps_lines,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ps_lines, dim3(j1 - j0), dim3(kPsThreads), shm, s, j0, p.Nr, p.dr, t.fov,
+                     p.q * p.os, t.Lmax, p.perm, t.n, p.nrhoSorted, p.lineOffSorted, t.cosTab,
+                     taper, w, p.part);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_lines_out(const DevPlan& p, void* lines, hipStream_t s) {
   dim3 grid(4, p.Pall);

@@ -33,7 +33,7 @@ EXPORTS = (
     "wkern_abi_version", "wkern_layout_desc", "wkern_plan", "wkern_layout",
     "wkern_generate", "wkern_generate_truncated", "wkern_generate_radial", "wkern_grad", "wkern_set_profiling",
     "wkern_stage_times", "wkern_plan_info", "wkern_set_variant",
-    "wkern_set_chunks", "wkern_set_graph", "wkern_destroy",
+    "wkern_set_chunks", "wkern_set_graph", "wkern_set_engine", "wkern_destroy",
     "wkern_strerror", "wkern_last_error",
     "wkern_fft2d_plan", "wkern_fft2d_generate", "wkern_fft2d_destroy",
     "wkern_wpartition_workspace", "wkern_wpartition",
@@ -105,6 +105,8 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_set_variant.argtypes = [vp, ctypes.c_int32]
     lib.wkern_set_graph.restype = ctypes.c_int
     lib.wkern_set_graph.argtypes = [vp, ctypes.c_int32]
+    lib.wkern_set_engine.restype = ctypes.c_int
+    lib.wkern_set_engine.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     lib.wkern_set_chunks.restype = ctypes.c_int
     lib.wkern_set_chunks.argtypes = [vp, ctypes.c_int32]
     lib.wkern_destroy.restype = ctypes.c_int
@@ -314,6 +316,16 @@ class Plan:
 
     def set_graph(self, enable: bool):
         _check(load_library().wkern_set_graph(self._h, 1 if enable else 0))
+
+    ENGINES = {"matrix": 0, "projection_slice": 1}
+    PS_WORKSPACE = {"max_support": 0, "per_plane": 1}
+
+    def set_engine(self, engine: str = "matrix", workspace: str = "per_plane"):
+        """Radial-line engine: "matrix" (HT matrix on the matrix cores) or
+        "projection_slice" (section 4.3.1, FP64), with the projection-slice
+        workspace per plane or fixed at the maximum support."""
+        _check(load_library().wkern_set_engine(self._h, self.ENGINES[engine],
+                                               self.PS_WORKSPACE[workspace]))
 
     def set_chunks(self, chunks: int):
         _check(load_library().wkern_set_chunks(self._h, int(chunks)))

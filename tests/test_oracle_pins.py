@@ -443,6 +443,6 @@ def test_projslice_agrees_with_matrix_form_on_smooth_edge():
 @pytest.mark.parametrize("s,os_,q,min_w,n", [(7, 8, 1, None, 8), (9, 8, 1, None, 16),
                                              (255, 8, 1, None, 256), (31, 1, 1, None, 64),
                                              (1, 1, 1, None, 8), (7, 8, 1, 255, 256),
-                                             (31, 4, 2, None, 32)])
+                                             (31, 4, 2, None, 32), (1, 8, 1, None, 2)])
 def test_projslice_workspace_size(s, os_, q, min_w, n):
     assert PS.workspace_size(s, os_, q, min_w) == n
