@@ -48,6 +48,7 @@ def _parse():
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-fft", action="store_true")
     ap.add_argument("--fft-steps", type=int, default=2)
+    ap.add_argument("--skip-projslice", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="counter pass: one warm and one measured generate of the split path, "
                          "then a 2 GiB device copy as the reference for the byte counters")
@@ -156,6 +157,42 @@ def _fft_paths(wl, taper, w, out, steps):
         plan.close()
         res[f"fft2d_{mode}"] = {"kernels_per_s": wl.n_planes / wall, "ms_per_step": 1000.0 * wall,
                                 "steps": steps, "max_rel_err_sampled_vs_2d_twin": worst}
+    return res
+
+
+def _projslice_paths(wl, taper, w, out, steps):
+    """The projection-slice engine (section 4.3.1) on the same batch: per-plane
+    and fixed workspaces.  Errors on sampled planes against the oracle's
+    projection-slice chain (parity) and against the matrix-form oracle (the
+    difference between the two discretisations)."""
+    from oracle import fft2d as F
+    from oracle import hankel as H
+    from oracle import projslice as PS
+    from paper_1904_08463_amd import Plan
+    fov = wl.image_size * wl.cellsize
+    tfn = F.taper_from_samples(wl.taper, 0.5 * fov)
+    order = np.argsort(wl.support, kind="stable")
+    check = sorted(set(order[[0, 8000, 16000]].tolist()))
+    ref_h, _ = H.generate_workload(wl, planes=check)
+    res = {}
+    for mode in ("per_plane", "max_support"):
+        plan = Plan.from_workload(wl, precision="bf16x6")
+        plan.set_engine("projection_slice", mode)
+        wall, stages = _time_path(plan, taper, w, out, steps, 1)
+        fixed = wl.max_support if mode == "max_support" else None
+        ref_ps, _ = PS.generate(tfn, wl.w[check], wl.support[check], wl.oversampling, fov,
+                                wl.radial_refine, wl.interp, fixed)
+        e_ps = e_h = 0.0
+        for j, p in enumerate(check):
+            got = out[int(plan.offsets[p]):int(plan.offsets[p + 1])].cpu().numpy()
+            a, b = ref_ps[j].reshape(-1), ref_h[j].reshape(-1)
+            e_ps = max(e_ps, float(np.max(np.abs(got - a)) / np.max(np.abs(a))))
+            e_h = max(e_h, float(np.max(np.abs(got - b)) / np.max(np.abs(b))))
+        res[f"projection_slice_{mode}"] = {
+            "kernels_per_s": wl.n_planes / (wall / steps), "ms_per_step": 1000.0 * wall / steps,
+            "stage_ms": stages, "max_rel_err_sampled_vs_projslice_oracle": e_ps,
+            "max_rel_diff_sampled_vs_matrix_form_oracle": e_h}
+        plan.close()
     return res
 
 
@@ -294,6 +331,8 @@ def main():
 
     if not args.skip_fft:
         paths.update(_fft_paths(wl, taper, w, out, args.fft_steps))
+    if not args.skip_projslice:
+        paths.update(_projslice_paths(wl, taper, w, out, args.steps))
     paths["wpartition"] = _wpartition_paths(args.steps)
 
     line = {
