@@ -10,6 +10,8 @@
 //   k_spline       spline coefficients of each radial line (section 4.3.2);
 //   k_resample     oversampled 2D kernels over the circular support
 //                  (section 4.4, Algorithm 2), in wkern_resample.hip.
+#include <type_traits>
+
 #include "wkern_internal.h"
 #include "wkern_radial.h"
 
@@ -596,6 +598,14 @@ __global__ __launch_bounds__(256) void k_contract_f32_lds(
 // the tile for those nodes (3 BF16 terms each) are loaded into ring slot
 // s % NS while the waves compute from older slots; NS - 1 stages are in
 // flight.  Every kSubChunk nodes the FP32 matrix-core sums go to FP64.
+//
+// Keeping the loads in flight takes two things the plain idioms defeat:
+// every slot is its own LDS object, and the slot a stage touches is a
+// compile-time constant (the stage loop is unrolled by NS), so the compiler
+// can tell that the reads of one slot do not depend on the loads into the
+// others; and the workgroup barrier is a bare s_barrier after an explicit
+// vmcnt wait for this stage's loads only, since a barrier with a
+// workgroup-scope fence waits for every outstanding load.
 // --------------------------------------------------------------------------
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
@@ -616,14 +626,18 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_ring(
   constexpr int SU = AU + BN * 2 * 3;       // uint4 per stage
   constexpr int LW = (SU + 255) / 256;      // load instructions per wave per stage
   constexpr int SLOT = LW * 256;            // padded slot size (uint4)
+  static_assert(NS == 3 || NS == 4, "ring depth");
   static_assert(LW * (NS - 2) < 64, "too many loads in flight for vmcnt");
-  __shared__ uint4 ring[NS][SLOT];
+  __shared__ uint4 ring0[SLOT];
+  __shared__ uint4 ring1[SLOT];
+  __shared__ uint4 ring2[SLOT];
+  __shared__ uint4 ring3[NS == 4 ? SLOT : 1];
 
   const Tile t = tiles[blockIdx.x];
   if (t.row0 < 0) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave / WC;
   const int wc = wave - wr * WC;
   const int hb = lane >> 5;
@@ -651,16 +665,7 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_ring(
       src[l] = Bsplit + ((size_t)(t.col0 + col) * ng + kg0 + grp) * 3 + term;
     }
   }
-  const int nst = kchunk / 16;
-  auto issue = [&](int stage) {
-    uint4* slot = &ring[stage % NS][0];
-#pragma unroll
-    for (int l = 0; l < LW; ++l)
-      __builtin_amdgcn_global_load_lds((const void*)(src[l] + (size_t)stage * 6),
-                                       (__attribute__((address_space(3))) void*)(slot + 256 * l +
-                                                                                 64 * wave),
-                                       16, 0, 0);
-  };
+  const int nst = kchunk / 16;  // a multiple of 16
 
   double accd[RBW * CBW][16];
   f32x16 hi[RBW * CBW], lo[RBW * CBW];
@@ -672,21 +677,43 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_ring(
       hi[b][r] = 0.f;
       lo[b][r] = 0.f;
     }
-  // active row blocks of this wave (uniform per wave)
   const int rbBase = wr * RBW;
 
+  auto slot_of = [&](auto kc) -> uint4* {
+    constexpr int K = decltype(kc)::value;
+    if constexpr (K == 0) return ring0;
+    else if constexpr (K == 1) return ring1;
+    else if constexpr (K == 2) return ring2;
+    else return ring3;
+  };
+  auto issue = [&](auto kc, int stage) {
+    uint4* slot = slot_of(kc);
 #pragma unroll
-  for (int s = 0; s < NS - 1; ++s)
-    if (s < nst) issue(s);
-
-  for (int s = 0; s < nst; ++s) {
+    for (int l = 0; l < LW; ++l)
+      __builtin_amdgcn_global_load_lds((const void*)(src[l] + (size_t)stage * 6),
+                                       (__attribute__((address_space(3))) void*)(slot + 256 * l +
+                                                                                 64 * wave),
+                                       16, 0, 0);
+  };
+  // workgroup barrier without a memory fence; the empty asm statements keep
+  // the compiler from moving LDS accesses across it
+  auto barrier = [&]() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  auto step = [&](auto kc, int s) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int KN = (K + NS - 1) % NS;  // slot of stage s + NS - 1
+    // this wave's loads of stage s have landed; after the barrier so have
+    // every wave's, and every wave is done reading slot KN (stage s - 1)
     if (s + NS - 2 < nst)
       wait_vmcnt<LW * (NS - 2)>();
     else
       wait_vmcnt<0>();
-    __syncthreads();
-    if (s + NS - 1 < nst) issue(s + NS - 1);
-    const uint4* slot = &ring[s % NS][0];
+    barrier();
+    if (s + NS - 1 < nst) issue(std::integral_constant<int, KN>{}, s + NS - 1);
+    const uint4* slot = slot_of(kc);
     bf16x8 bq[CBW][3];
 #pragma unroll
     for (int cb = 0; cb < CBW; ++cb) {
@@ -695,22 +722,33 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_ring(
       bq[cb][1] = as_bf16x8(bp[1]);
       bq[cb][2] = as_bf16x8(bp[2]);
     }
+    bf16x8 aq[RBW][3];
 #pragma unroll
     for (int rb = 0; rb < RBW; ++rb) {
-      if (rbBase + rb >= t.rbN) break;
       const uint4* ap = slot + (hb * BM + (rbBase + rb) * 32 + rr) * 3;
-      const bf16x8 a0 = as_bf16x8(ap[0]);
-      const bf16x8 a1 = as_bf16x8(ap[1]);
-      const bf16x8 a2 = as_bf16x8(ap[2]);
+      aq[rb][0] = as_bf16x8(ap[0]);
+      aq[rb][1] = as_bf16x8(ap[1]);
+      aq[rb][2] = as_bf16x8(ap[2]);
+    }
+    // products interleaved over the output blocks so consecutive MFMAs are
+    // independent; row blocks past the tile's last row compute on padded
+    // rows of M and are not stored
 #pragma unroll
-      for (int cb = 0; cb < CBW; ++cb) {
-        const int b = rb * CBW + cb;
-        lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bq[cb][2], lo[b], 0, 0, 0);
-        lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bq[cb][1], lo[b], 0, 0, 0);
-        lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, bq[cb][0], lo[b], 0, 0, 0);
-        lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bq[cb][1], lo[b], 0, 0, 0);
-        lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bq[cb][0], lo[b], 0, 0, 0);
-        hi[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bq[cb][0], hi[b], 0, 0, 0);
+    for (int term = 0; term < 6; ++term) {
+#pragma unroll
+      for (int rb = 0; rb < RBW; ++rb) {
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb) {
+          const int b = rb * CBW + cb;
+          switch (term) {
+            case 0: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][2], lo[b], 0, 0, 0); break;
+            case 1: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][1], lo[b], 0, 0, 0); break;
+            case 2: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[cb][0], lo[b], 0, 0, 0); break;
+            case 3: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][1], lo[b], 0, 0, 0); break;
+            case 4: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][0], lo[b], 0, 0, 0); break;
+            default: hi[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][0], hi[b], 0, 0, 0); break;
+          }
+        }
       }
     }
     if (((s + 1) * 16) % kSubChunk == 0) {
@@ -722,6 +760,24 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_ring(
           hi[b][r] = 0.f;
           lo[b][r] = 0.f;
         }
+    }
+  };
+
+  issue(std::integral_constant<int, 0>{}, 0);
+  issue(std::integral_constant<int, 1>{}, 1);
+  if constexpr (NS == 4) {
+    issue(std::integral_constant<int, 2>{}, 2);
+    for (int s0 = 0; s0 < nst; s0 += 4) {
+      step(std::integral_constant<int, 0>{}, s0);
+      step(std::integral_constant<int, 1>{}, s0 + 1);
+      step(std::integral_constant<int, 2>{}, s0 + 2);
+      step(std::integral_constant<int, 3>{}, s0 + 3);
+    }
+  } else {
+    for (int s0 = 0; s0 < nst; s0 += 3) {
+      step(std::integral_constant<int, 0>{}, s0);
+      if (s0 + 1 < nst) step(std::integral_constant<int, 1>{}, s0 + 1);
+      if (s0 + 2 < nst) step(std::integral_constant<int, 2>{}, s0 + 2);
     }
   }
 
