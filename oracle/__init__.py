@@ -21,6 +21,8 @@ Wide-field Imaging"):
 * ``projslice`` -- the paper's own Hankel engine (section 4.3.1): 1D
   projection of the workspace screen, zero-padded 1D FFT, then the same
   interpolation as ``hankel``.
+* ``gridding`` -- the step that consumes the kernels in Algorithm 2:
+  each record's oversampled sub-kernel added onto the uv grid.
 * ``wpartition`` -- the w-plane partition that opens Algorithms 1 and 2:
   sort by (absolute) w, equal-size planes, average or median w per plane.
 * ``adjoint``  -- the exact gradient of a real loss of the kernel cache with
@@ -30,4 +32,4 @@ Wide-field Imaging"):
 Parity status of each function is listed in its docstring.  Readings of the
 paper where it is silent or ambiguous are listed in ``hankel``'s header.
 """
-from . import hankel, fft2d, adjoint, projslice, wpartition  # noqa: F401
+from . import hankel, fft2d, adjoint, gridding, projslice, wpartition  # noqa: F401

@@ -304,6 +304,77 @@ def multichannel_w(w: np.ndarray, n_chan: int, f_lo: float = 1.0, f_hi: float = 
     return (np.asarray(w, dtype=np.float64)[None, :] * (nu / f_lo)[:, None]).reshape(-1)
 
 
+def point_source_vis(u, v, w, sources) -> np.ndarray:
+    """Visibilities of point sources (amplitude, l, m):
+    V = sum A exp(-j 2 pi (u l + v m + w (n - 1))), n = sqrt(1 - l^2 - m^2)
+    (the measurement equation of section 1 with the w-term kept); complex64."""
+    vis = np.zeros(np.shape(u), dtype=np.complex128)
+    for a, l, m in sources:
+        n = math.sqrt(1.0 - l * l - m * m)
+        vis += a * np.exp(-2j * math.pi * (u * l + v * m + w * (n - 1.0)))
+    return vis.astype(np.complex64)
+
+
+def diagonal_sources(n_src: int = 5, max_deg: float = 12.0):
+    """Equal 1 Jy sources on the image diagonal from the centre out to
+    max_deg (the 5DIAG layout of section 5)."""
+    out = []
+    for k in range(n_src):
+        rad = math.radians(max_deg) * k / max(n_src - 1, 1)
+        out.append((1.0, rad / math.sqrt(2.0), -rad / math.sqrt(2.0)))
+    return out
+
+
+@dataclass
+class GridWorkload:
+    name: str
+    image_size: int
+    cellsize: float
+    grid_size: int
+    n_radial: int
+    oversampling: int
+    n_planes: int
+    max_support: int
+    taper: np.ndarray       # float32 [Nr]
+    u: np.ndarray           # float64 [n] wavelengths
+    v: np.ndarray
+    w: np.ndarray
+    vis: np.ndarray         # complex64 [n]
+    frac: float = 0.01      # kernel truncation fraction
+
+
+def grid_paper(n_times: int = 1440, n_planes: int = 128, n_radial: int = 4096) -> GridWorkload:
+    """The paper's imaging setting on the synthetic records: IM-S (2048^2 at
+    60 arcsec), 128 |w|-planes, os 8, maximum support 255 (half-width 127),
+    1% truncation, Gaussian AA taper (sigma = r_max / 6), five 1 Jy sources on
+    the diagonal out to 12 deg; 505440 records at 74 MHz."""
+    n, cell = 2048, 60.0 * ARCSEC
+    r_max = 0.5 * n * cell
+    enu = y_array()
+    u, v, w = uvw_tracks(enu, 74e6, 47.339, 34.079, n_times)
+    vis = point_source_vis(u, v, w, diagonal_sources())
+    fn = gaussian_taper(r_max / 6.0)
+    return GridWorkload("grid_paper", n, cell, n, n_radial, 8, n_planes, 255,
+                        sample_taper(fn, n_radial, r_max), u, v, w, vis)
+
+
+def grid_small(seed: int = 0, n_rec: int = 600, n_planes: int = 6, grid_size: int = 96,
+               os_: int = 4, max_support: int = 15) -> GridWorkload:
+    """Small gridding case for full-grid parity: plain geometry (r_max 0.05),
+    random records inside the grid and random complex visibilities."""
+    rng = np.random.default_rng(SEED + seed)
+    n, cell = 128, 7.8125e-4
+    du = 1.0 / (n * cell)
+    half = 0.5 * grid_size * du
+    u = rng.uniform(-0.8 * half, 0.8 * half, n_rec)
+    v = rng.uniform(-0.8 * half, 0.8 * half, n_rec)
+    w = rng.uniform(-1000.0, 1000.0, n_rec)
+    vis = (rng.normal(size=n_rec) + 1j * rng.normal(size=n_rec)).astype(np.complex64)
+    fn = gaussian_taper(0.02)
+    return GridWorkload(f"grid_small{seed}", n, cell, grid_size, 128, os_, n_planes, max_support,
+                        sample_taper(fn, 128, 0.5 * n * cell), u, v, w, vis)
+
+
 WORKLOADS = {
     "plain": plain,
     "paper": paper,
