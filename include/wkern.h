@@ -183,6 +183,51 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
                         const void* grad_out, float* grad_taper, double* grad_w,
                         void* stream);
 
+/* -------------------------------------------------------------------------
+ * Gridding with the kernels (Algorithm 2, last step of each w-plane): every
+ * visibility record adds V K to the S x S grid cells around it, K the nearest
+ * oversampled sub-kernel of the record's plane, conjugated when the record's
+ * w is negative (section 4.1).  Grid: N x N cells of du = 1 / (image_size
+ * cellsize); cell (ix, iy) holds uv = ((ix - N/2) du, (iy - N/2) du), row
+ * major (v, then u).  A record at x = u / du + N/2 uses cell i = floor(x) and
+ * sub-kernel f = floor((x - i) os + 1/2) (f = os moves to i + 1, f = 0); cell
+ * i + a - h receives sample a of sub-kernel f (both axes; FP64).  Cells
+ * outside the grid are skipped.
+ * ------------------------------------------------------------------------- */
+
+/* Steps 1-3 without the resample: the radial lines and their spline
+ * coefficients stay in the plan for a fused wkern_grid, so no kernel cache
+ * is written.  frac > 0 applies the truncation rule of
+ * wkern_generate_truncated; frac == 0 keeps the planned supports.
+ * support_out: device int32 [P] (written): the supports wkern_grid should
+ * use.  Asynchronous on `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY,
+ * DEVICE. */
+wkern_status wkern_prepare_lines(wkern_plan_t plan, const float* taper, const double* w,
+                                 double frac, int32_t* support_out, void* stream);
+
+/* u, v, w:      device double [n_records], wavelengths.
+ * vis:          device complex64 [n_records].
+ * order, plane_start: the partition (wkern_wpartition) over the plan's P
+ *               planes: plane m grids records order[plane_start[m] ..
+ *               plane_start[m + 1] - 1].
+ * support:      device int32 [P], odd widths; each at most the planned one.
+ * cache:        NULL: fused, the kernel values come from the spline
+ *               coefficients of the plan's last wkern_prepare_lines or
+ *               generate call (same stream, same taper and w); otherwise a
+ *               device complex64 kernel cache with plane m at
+ *               cache_offsets[m] (device int64 [P + 1]) laid out
+ *               [os][os][S][S] with S = support[m] (what wkern_generate /
+ *               wkern_generate_truncated write).
+ * grid_size:    N, even.
+ * grid:         device complex64 [N][N], accumulated into (the caller clears
+ *               it); FP32 atomic sums, so the last bits depend on timing.
+ * Asynchronous on `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+wkern_status wkern_grid(wkern_plan_t plan, const double* u, const double* v, const double* w,
+                        const void* vis, int64_t n_records, const int32_t* order,
+                        const int64_t* plane_start, const int32_t* support, const void* cache,
+                        const int64_t* cache_offsets, int32_t grid_size, void* grid,
+                        void* stream);
+
 /* Engine of the radial-line step (steps 1-2).
  * WKERN_ENGINE_MATRIX (default): the discrete HT matrix times the sampled
  *   screen on the matrix cores (section 4.3), in the plan's precision.

@@ -25,6 +25,7 @@ SOURCES = [
     ("wkern_fft2d.hip", True),
     ("wkern_resample.hip", True),
     ("wkern_wpartition.hip", True),
+    ("wkern_grid.hip", True),
 ]
 LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
 

@@ -189,6 +189,9 @@ struct wkern_plan_s {
   GradScratch grad{};
   bool gradReady = false;
 
+  // gridding work-item table, allocated on the first wkern_grid call
+  int32_t* gridChunks = nullptr;
+
   // radial-line engine: 0 matrix form (HT matrix on the matrix cores),
   // 1 projection-slice; the latter writes one K-chunk, so its spline and
   // line views carry nkc = 1
@@ -804,6 +807,20 @@ wkern_status wkern_set_graph(wkern_plan_t plan, int32_t enable) {
   return WKERN_OK;
 }
 
+static wkern_status ensure_trunc_scratch(wkern_plan_t plan) {
+  if (plan->truncReady) return WKERN_OK;
+  const DevPlan& g = plan->dp;
+  TruncScratch& ts = plan->trunc;
+  wkern_status s;
+  if ((s = plan->alloc(&ts.hTrunc, (size_t)g.P, "truncation table")) != WKERN_OK) return s;
+  if ((s = plan->alloc(&ts.unitStart, (size_t)g.Pall + 1, "truncation table")) != WKERN_OK)
+    return s;
+  if ((s = plan->upload(&ts.sortedPos, plan->sortedPosOfCaller, "truncation table")) != WKERN_OK)
+    return s;
+  plan->truncReady = true;
+  return WKERN_OK;
+}
+
 wkern_status wkern_generate_truncated(wkern_plan_t plan, const float* taper, const double* w,
                                       double frac, void* out, int64_t out_capacity,
                                       int32_t* support_out, int64_t* offsets_out, void* stream) {
@@ -816,21 +833,58 @@ wkern_status wkern_generate_truncated(wkern_plan_t plan, const float* taper, con
     return fail(WKERN_ERR_INVALID_ARG, "out_capacity %lld < %lld (untruncated cache)",
                 (long long)out_capacity, (long long)plan->offsets.back());
   DeviceGuard guard(plan->desc.device);
-  const DevPlan& g = plan->dp;
-  if (!plan->truncReady) {
-    TruncScratch& ts = plan->trunc;
-    if ((s = plan->alloc(&ts.hTrunc, (size_t)g.P, "truncation table")) != WKERN_OK) return s;
-    if ((s = plan->alloc(&ts.unitStart, (size_t)g.Pall + 1, "truncation table")) != WKERN_OK)
-      return s;
-    if ((s = plan->upload(&ts.sortedPos, plan->sortedPosOfCaller, "truncation table")) != WKERN_OK)
-      return s;
-    plan->truncReady = true;
-  }
+  if ((s = ensure_trunc_scratch(plan)) != WKERN_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   if ((s = enqueue_lines(plan, taper, w, st)) != WKERN_OK) return s;
   WK_HIP(launch_resample_truncated(lines_view(plan), plan->trunc, frac, support_out, offsets_out,
                                    out, st),
          "truncated resample launch");
+  return WKERN_OK;
+}
+
+wkern_status wkern_prepare_lines(wkern_plan_t plan, const float* taper, const double* w,
+                                 double frac, int32_t* support_out, void* stream) {
+  clear_error();
+  wkern_status s = check_gen_args(plan, taper, w, support_out);
+  if (s != WKERN_OK) return s;
+  if (!(frac >= 0.0 && frac < 1.0)) return fail(WKERN_ERR_INVALID_ARG, "frac %g not in [0, 1)", frac);
+  DeviceGuard guard(plan->desc.device);
+  if (frac > 0.0 && (s = ensure_trunc_scratch(plan)) != WKERN_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = enqueue_lines(plan, taper, w, st)) != WKERN_OK) return s;
+  const DevPlan view = lines_view(plan);
+  int32_t* hT = frac > 0.0 ? plan->trunc.hTrunc : nullptr;
+  WK_HIP(launch_spline(view, 0, view.P, st, frac, hT), "spline launch");
+  WK_HIP(launch_supports(view, hT, hT ? plan->trunc.sortedPos : nullptr, support_out, st),
+         "supports launch");
+  return WKERN_OK;
+}
+
+wkern_status wkern_grid(wkern_plan_t plan, const double* u, const double* v, const double* w,
+                        const void* vis, int64_t n_records, const int32_t* order,
+                        const int64_t* plane_start, const int32_t* support, const void* cache,
+                        const int64_t* cache_offsets, int32_t grid_size, void* grid,
+                        void* stream) {
+  clear_error();
+  if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
+  if (!u || !v || !w || !vis || !order || !plane_start || !support || !grid)
+    return fail(WKERN_ERR_INVALID_ARG, "NULL argument");
+  if (cache && !cache_offsets) return fail(WKERN_ERR_INVALID_ARG, "cache_offsets is NULL");
+  if (n_records < 0 || n_records > 0x7FFFFFFF)
+    return fail(WKERN_ERR_INVALID_ARG, "n_records %lld out of range", (long long)n_records);
+  if (grid_size < 2 || grid_size > 65536 || grid_size % 2)
+    return fail(WKERN_ERR_INVALID_ARG, "grid_size %d must be even, 2 .. 65536", grid_size);
+  if (n_records == 0) return WKERN_OK;
+  DeviceGuard guard(plan->desc.device);
+  wkern_status s;
+  if (!plan->gridChunks &&
+      (s = plan->alloc(&plan->gridChunks, (size_t)plan->dp.Pall + 1, "gridding table")) != WKERN_OK)
+    return s;
+  const double du = 1.0 / ((double)plan->desc.image_size * plan->desc.cellsize);
+  WK_HIP(launch_grid(lines_view(plan), plan->gridChunks, u, v, w, vis, n_records, order,
+                     plane_start, support, cache, cache_offsets, grid_size, du, grid,
+                     (hipStream_t)stream),
+         "gridding launch");
   return WKERN_OK;
 }
 

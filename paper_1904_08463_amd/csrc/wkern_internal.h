@@ -155,6 +155,16 @@ hipError_t launch_resample_truncated(const DevPlan& p, const TruncScratch& ts, d
 hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStream_t s);
 hipError_t launch_lines_out(const DevPlan& p, void* lines, hipStream_t s);
 
+// Plane supports after wkern_prepare_lines (truncated when hTrunc is given).
+hipError_t launch_supports(const DevPlan& p, const int32_t* hTrunc, const int32_t* sortedPos,
+                           int32_t* out, hipStream_t s);
+// Gridding with the plan's kernels: fused (cache == nullptr, values from the
+// spline intervals) or from a kernel cache; chunkStart is [Pall + 1] scratch.
+hipError_t launch_grid(const DevPlan& p, int32_t* chunkStart, const double* u, const double* v,
+                       const double* w, const void* vis, int64_t n, const int32_t* order,
+                       const int64_t* planeStart, const int32_t* support, const void* cache,
+                       const int64_t* cacheOff, int N, double du, void* grid, hipStream_t s);
+
 // Tables of the projection-slice engine (built when the engine is selected).
 struct PsTables {
   int32_t* n;       // [P] workspace width N_ws of sorted plane j (a power of two)

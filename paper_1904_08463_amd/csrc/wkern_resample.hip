@@ -24,38 +24,6 @@ namespace {
 // u slightly outside [0, 1), where the neighbouring cubic piece agrees.
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ f32x2 cache_value(int X, int Y, int lim, float q, int nmax,
-                                             const float4* __restrict__ sc) {
-  const int d2 = X * X + Y * Y;
-  f32x2 v = {0.f, 0.f};
-  if (d2 <= lim) {
-    int k;
-    float uu;
-    radial_pos(d2, q, nmax, k, uu);
-    const float4 cr = sc[2 * k];
-    const float4 ci = sc[2 * k + 1];
-    v.x = fmaf(uu, fmaf(uu, fmaf(uu, cr.w, cr.z), cr.y), cr.x);
-    v.y = fmaf(uu, fmaf(uu, fmaf(uu, ci.w, ci.z), ci.y), ci.x);
-  }
-  return v;
-}
-
-// Exact n / d for n < 2^24 and d < 2^16 from an FP32 reciprocal estimate
-// (off by at most one) and one integer correction.
-__device__ __forceinline__ int div_small(int n, int d, float inv, int& rem) {
-  int qt = (int)((float)n * inv);
-  int r = n - qt * d;
-  if (r < 0) {
-    qt -= 1;
-    r += d;
-  } else if (r >= d) {
-    qt += 1;
-    r -= d;
-  }
-  rem = r;
-  return qt;
-}
-
 // Writes elements [e0, e1) of one plane (its spline intervals already in sc).
 __device__ __forceinline__ void resample_range(const PlaneInfo& pi, int e0, int e1, int os,
                                                float invOs, float q,

@@ -37,6 +37,7 @@ EXPORTS = (
     "wkern_strerror", "wkern_last_error",
     "wkern_fft2d_plan", "wkern_fft2d_generate", "wkern_fft2d_destroy",
     "wkern_wpartition_workspace", "wkern_wpartition",
+    "wkern_prepare_lines", "wkern_grid",
 )
 
 
@@ -121,6 +122,11 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_fft2d_generate.argtypes = [vp, vp, vp, vp, vp]
     lib.wkern_fft2d_destroy.restype = ctypes.c_int
     lib.wkern_fft2d_destroy.argtypes = [vp]
+    lib.wkern_prepare_lines.restype = ctypes.c_int
+    lib.wkern_prepare_lines.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
+    lib.wkern_grid.restype = ctypes.c_int
+    lib.wkern_grid.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp,
+                               ctypes.c_int32, vp, vp]
     lib.wkern_wpartition_workspace.restype = ctypes.c_int
     lib.wkern_wpartition_workspace.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
     lib.wkern_wpartition.restype = ctypes.c_int
@@ -316,6 +322,39 @@ class Plan:
 
     def set_graph(self, enable: bool):
         _check(load_library().wkern_set_graph(self._h, 1 if enable else 0))
+
+    def prepare_lines(self, taper, w, frac=0.0, support_out=None, stream=None):
+        """Lines and spline coefficients kept in the plan for a fused grid();
+        returns the device int32 supports (truncated when frac > 0)."""
+        import torch
+        self._check_inputs(taper, w)
+        if support_out is None:
+            support_out = torch.empty(self.n_planes, dtype=torch.int32, device=taper.device)
+        _check(load_library().wkern_prepare_lines(self._h, _ptr(taper), _ptr(w), ctypes.c_double(frac),
+                                                  _ptr(support_out), _stream_handle(stream)))
+        return support_out
+
+    def grid(self, u, v, w, vis, order, plane_start, support, grid, cache=None,
+             cache_offsets=None, stream=None):
+        """Add every record's kernel footprint onto grid (complex64 [N, N]):
+        fused from the prepared lines (cache None) or from a kernel cache."""
+        import torch
+        for t, dt in ((u, torch.float64), (v, torch.float64), (w, torch.float64),
+                      (vis, torch.complex64), (order, torch.int32), (plane_start, torch.int64),
+                      (support, torch.int32), (grid, torch.complex64)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("gridding arguments must be contiguous device tensors of "
+                                 "the documented dtypes")
+        if grid.dim() != 2 or grid.shape[0] != grid.shape[1]:
+            raise ValueError("grid must be square")
+        if cache is not None and (cache.dtype != torch.complex64 or cache_offsets is None):
+            raise ValueError("cache must be complex64 with device cache_offsets")
+        _check(load_library().wkern_grid(
+            self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(vis), u.numel(), _ptr(order),
+            _ptr(plane_start), _ptr(support), None if cache is None else _ptr(cache),
+            None if cache_offsets is None else _ptr(cache_offsets), grid.shape[0], _ptr(grid),
+            _stream_handle(stream)))
+        return grid
 
     ENGINES = {"matrix": 0, "projection_slice": 1}
     PS_WORKSPACE = {"max_support": 0, "per_plane": 1}

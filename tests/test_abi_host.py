@@ -98,6 +98,9 @@ def test_null_arguments(lib):
     assert lib.wkern_generate_truncated(None, None, None, 0.01, None, 0, None, None, None) == 1
     assert lib.wkern_generate_radial(None, None, None, None, None) == 1
     assert lib.wkern_wpartition(None, 10, 2, 1, 0, None, 0, None, None, None, None) == 1
+    assert lib.wkern_prepare_lines(None, None, None, 0.0, None, None) == 1
+    assert lib.wkern_grid(None, None, None, None, None, 0, None, None, None, None, None, 64,
+                          None, None) == 1
     n = ctypes.c_size_t()
     assert lib.wkern_wpartition_workspace(0, ctypes.byref(n)) == 1
     assert lib.wkern_wpartition_workspace(1 << 31, ctypes.byref(n)) == 4
