@@ -196,6 +196,69 @@ def _projslice_paths(wl, taper, w, out, steps):
     return res
 
 
+def _gridding_paths(steps):
+    """The paper's imaging setting on the synthetic records (IM-S 2048^2 at 60
+    arcsec, 128 |w|-planes of 505440 records at 74 MHz, os 8, supports up to
+    255 with 1% truncation, split-BF16): partition, kernels and gridding,
+    once with the fused consumer (no kernel cache) and once through a
+    written cache."""
+    import torch
+    import workloads as W
+    from paper_1904_08463_amd import Plan, wpartition, wpartition_workspace
+    gw = W.grid_paper()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    u, v, w, vis, taper = dev(gw.u), dev(gw.v), dev(gw.w), dev(gw.vis), dev(gw.taper)
+    n = gw.grid_size
+    plan = Plan(gw.image_size, gw.cellsize, gw.n_radial, gw.oversampling,
+                [gw.max_support] * gw.n_planes, gw.max_support, precision="bf16x6")
+    ws = torch.empty(wpartition_workspace(gw.u.size), dtype=torch.uint8, device="cuda")
+    grid = torch.zeros((n, n), dtype=torch.complex64, device="cuda")
+    sup = torch.empty(gw.n_planes, dtype=torch.int32, device="cuda")
+    cache = torch.empty(int(plan.offsets[-1]), dtype=torch.complex64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def fused():
+        order, start, wp = wpartition(w, gw.n_planes, workspace=ws)
+        ev[0].record()
+        plan.prepare_lines(taper, wp, frac=gw.frac, support_out=sup)
+        ev[1].record()
+        grid.zero_()
+        ev[2].record()
+        plan.grid(u, v, w, vis, order, start, sup, grid)
+        ev[3].record()
+
+    def cached():
+        order, start, wp = wpartition(w, gw.n_planes, workspace=ws)
+        ev[0].record()
+        _, s2, offs = plan.generate_truncated(taper, wp, gw.frac, out=cache)
+        ev[1].record()
+        grid.zero_()
+        ev[2].record()
+        plan.grid(u, v, w, vis, order, start, s2, grid, cache=cache, cache_offsets=offs)
+        ev[3].record()
+
+    res = {}
+    for name, fn in (("fused", fused), ("through_cache", cached)):
+        fn()
+        torch.cuda.synchronize()
+        kern = grd = 0.0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+            torch.cuda.synchronize()
+            kern += ev[0].elapsed_time(ev[1])
+            grd += ev[2].elapsed_time(ev[3])
+        wall = (time.perf_counter() - t0) / steps
+        res[name] = {"records_per_s": gw.u.size / wall, "ms_per_step": 1000.0 * wall,
+                     "kernels_ms": kern / steps, "gridding_ms": grd / steps,
+                     "n_records": int(gw.u.size), "n_planes": gw.n_planes, "grid": n}
+    sup_h = sup.cpu().numpy()
+    res["supports"] = [int(sup_h.min()), int(np.median(sup_h)), int(sup_h.max())]
+    res["cache_bytes_avoided"] = int(8 * gw.oversampling ** 2 * np.sum(sup_h.astype(np.int64) ** 2))
+    plan.close()
+    return res
+
+
 def _wpartition_paths(steps):
     """w-plane partition (sort by |w|, equal-size planes, mean |w|): the
     paper-shaped record set (505440 records, 128 planes) and the same records
@@ -334,6 +397,7 @@ def main():
     if not args.skip_projslice:
         paths.update(_projslice_paths(wl, taper, w, out, args.steps))
     paths["wpartition"] = _wpartition_paths(args.steps)
+    paths["gridding_paper_setting"] = _gridding_paths(args.steps)
 
     line = {
         "metric": "w-kernels/sec at <=1e-6 rel err (split-BF16 Hankel; FP32 Hankel beside it)",
