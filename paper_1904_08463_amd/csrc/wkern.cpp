@@ -556,10 +556,11 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   if ((s = pl->alloc(&g.M32, mElems, "M32")) != WKERN_OK) return s;
   if ((s = pl->alloc(&g.Msplit, mElems * 3, "Msplit")) != WKERN_OK) return s;
   const size_t bElems = (size_t)g.colsPad * g.NrPad;
-  if (g.precision == 0) {
-    if ((s = pl->alloc(&g.B32, bElems, "screen buffer")) != WKERN_OK) return s;
-    WK_HIP(hipMemset(g.B32, 0, bElems * sizeof(float)), "hipMemset");
-  } else {
+  // the FP32 screen serves the FP32 path and the split path's FP32-operand
+  // variants; the BF16 terms only the other split variants
+  if ((s = pl->alloc(&g.B32, bElems, "screen buffer")) != WKERN_OK) return s;
+  WK_HIP(hipMemset(g.B32, 0, bElems * sizeof(float)), "hipMemset");
+  if (g.precision == 1) {
     if ((s = pl->alloc(&g.Bsplit, bElems * 3, "screen buffer")) != WKERN_OK) return s;
     WK_HIP(hipMemset(g.Bsplit, 0, bElems * 3 * sizeof(uint16_t)), "hipMemset");
   }
@@ -583,11 +584,38 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   WK_HIP(hipEventCreateWithFlags(&pl->evJoinStore, hipEventDisableTiming), "hipEventCreate");
 
   // Autotune: time every contraction variant on this plan's own tile lists
-  // (timing does not depend on the screen values) and keep the fastest.
+  // (timing does not depend on the screen values), add the time of the
+  // screen kind it reads, and keep the fastest.
   {
     hipEvent_t a, b;
     WK_HIP(hipEventCreate(&a), "hipEventCreate");
     WK_HIP(hipEventCreate(&b), "hipEventCreate");
+    // screen kernels on a constant taper and w = 0 (the values do not matter)
+    float screenMs[2] = {0.f, 0.f};
+    {
+      float* tau = nullptr;
+      double* w0 = nullptr;
+      if ((s = pl->alloc(&tau, (size_t)g.Nr, "autotune input")) != WKERN_OK) return s;
+      if ((s = pl->alloc(&w0, (size_t)P, "autotune input")) != WKERN_OK) return s;
+      WK_HIP(hipMemset(tau, 0, (size_t)g.Nr * sizeof(float)), "hipMemset");
+      WK_HIP(hipMemset(w0, 0, (size_t)P * sizeof(double)), "hipMemset");
+      for (int kind = 0; kind < 2; ++kind) {
+        if (kind == 0 && g.precision == 0) continue;  // no BF16 terms in an FP32 plan
+        float bestK = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          WK_HIP(hipEventRecord(a, pl->sCompute), "hipEventRecord");
+          WK_HIP(launch_screen(g, 0, g.P, tau, w0, kind == 1, pl->sCompute), "autotune screen");
+          WK_HIP(hipEventRecord(b, pl->sCompute), "hipEventRecord");
+          WK_HIP(hipEventSynchronize(b), "hipEventSynchronize");
+          float ms = 0.f;
+          WK_HIP(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+          if (rep > 0) bestK = std::min(bestK, ms);
+        }
+        screenMs[kind] = bestK;
+      }
+      pl->release(tau);
+      pl->release(w0);
+    }
     float best = 1e30f;
     for (int v = 0; v < kNumVariants; ++v) {
       if (!variant_supported(g.precision, v)) {
@@ -605,6 +633,7 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
         WK_HIP(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
         if (rep > 0) bestV = std::min(bestV, ms);
       }
+      bestV += screenMs[variant_fp32_screen(g.precision, v) ? 1 : 0];
       pl->variantMs[v] = bestV;
       if (bestV < best) {
         best = bestV;
@@ -671,7 +700,8 @@ static wkern_status enqueue_lines(wkern_plan_t plan, const float* taper, const d
   const DevPlan& g = plan->dp;
   if (plan->engine == WKERN_ENGINE_MATRIX) {
     const int v = plan->variant;
-    WK_HIP(launch_screen(g, 0, g.P, taper, w, st), "screen launch");
+    WK_HIP(launch_screen(g, 0, g.P, taper, w, variant_fp32_screen(g.precision, v), st),
+           "screen launch");
     WK_HIP(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
            "contraction launch");
   } else {
@@ -692,7 +722,8 @@ static wkern_status enqueue_chunk(wkern_plan_t plan, int c, const float* taper, 
   wkern_status s;
   if (plan->engine == WKERN_ENGINE_MATRIX) {
     if ((s = plan->record_begin(0, compute, &r)) != WKERN_OK) return s;
-    WK_HIP(launch_screen(g, j0, j1, taper, w, compute), "screen launch");
+    WK_HIP(launch_screen(g, j0, j1, taper, w, variant_fp32_screen(g.precision, v), compute),
+           "screen launch");
     if ((s = record_end(r, compute)) != WKERN_OK) return s;
     if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;
     WK_HIP(launch_contract(g, v, plan->d_tiles[v] + t0, t1 - t0, compute), "contraction launch");

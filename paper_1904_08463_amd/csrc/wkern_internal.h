@@ -71,7 +71,11 @@ enum ContractVariant {
   kRing128x128 = 4,
   kRing64x256 = 5,
   kRing32x512 = 6,
-  kNumVariants = 7
+  // split-BF16 only: the same ring fed with FP32 M and FP32 screen columns,
+  // split into BF16 terms in registers (two thirds of the operand bytes)
+  kRingF128x128 = 7,
+  kRingF64x256 = 8,
+  kNumVariants = 9
 };
 
 // Tile geometry of a variant: rows per tile = 32 * rb, columns per tile.
@@ -84,6 +88,10 @@ ContractShape contract_shape(int variant);
 // The ring variants exist for the split-BF16 contraction only.
 inline bool variant_supported(int precision, int variant) {
   return variant < kRing128x128 || precision == 1;
+}
+// Whether a variant reads the FP32 screen (B32) rather than its BF16 terms.
+inline bool variant_fp32_screen(int precision, int variant) {
+  return precision == 0 || variant >= kRingF128x128;
 }
 
 // Planes of a pipeline chunk start at multiples of this (in sorted order),
@@ -136,8 +144,9 @@ hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* tap
                        hipStream_t s);
 hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s);
 hipError_t prepare_kernels(const DevPlan& p);
+// fp32: write the FP32 screen (B32) instead of its BF16 terms (Bsplit).
 hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, const double* w,
-                         hipStream_t s);
+                         bool fp32, hipStream_t s);
 hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int nTiles,
                            hipStream_t s);
 hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s, double frac = 0.0,

@@ -803,6 +803,198 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_ring(
 }
 
 // --------------------------------------------------------------------------
+// The same ring with FP32 operands: M32 rows and FP32 screen columns (4 bytes
+// per value instead of 3 BF16 terms) are staged, and every lane splits its
+// 8 values into three BF16 terms after reading them from LDS.  The split of
+// an FP32 value is exact: x = t0 + t1 + t2 with t0 = bf16(x),
+// t1 = bf16(x - t0), t2 = x - t0 - t1 (at most 8 significant bits left).
+// A stage holds 16 nodes of every row and column, 64 bytes each, as four
+// 16-byte quarters; quarter q of row r sits at slot position 4 r + (q ^ s),
+// s = (r / 4) % 4, so that the 16-byte reads of 16 consecutive rows fall in
+// distinct LDS banks.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void split_bf16x3(const float4& lo4, const float4& hi4, bf16x8& t0,
+                                             bf16x8& t1, bf16x8& t2) {
+  const float x[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 a = (__bf16)x[e];
+    const float r1 = x[e] - (float)a;
+    const __bf16 b = (__bf16)r1;
+    const float r2 = r1 - (float)b;
+    t0[e] = a;
+    t1[e] = b;
+    t2[e] = (__bf16)r2;
+  }
+}
+
+template <int WR, int WC, int RBW, int CBW>
+__global__ __launch_bounds__(256) void k_contract_bf16x6_ringf(
+    const Tile* __restrict__ tiles, int NrPad, int kchunk, int P, int lineTotal,
+    const float* __restrict__ M32, const float* __restrict__ B32,
+    const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
+    double* __restrict__ part) {
+  constexpr int NS = 4;
+  constexpr int BM = 32 * RBW * WR;
+  constexpr int BN = 32 * CBW * WC;
+  constexpr int AU = BM * 4;                // 16-byte quarters of M per stage
+  constexpr int SU = AU + BN * 4;           // quarters per stage
+  constexpr int LW = (SU + 255) / 256;      // load instructions per wave per stage
+  constexpr int SLOT = LW * 256;
+  static_assert(LW * (NS - 2) < 64, "too many loads in flight for vmcnt");
+  __shared__ float4 ring0[SLOT];
+  __shared__ float4 ring1[SLOT];
+  __shared__ float4 ring2[SLOT];
+  __shared__ float4 ring3[SLOT];
+
+  const Tile t = tiles[blockIdx.x];
+  if (t.row0 < 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave / WC;
+  const int wc = wave - wr * WC;
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+
+  // source of slot position u = 256 l + tid: position 4 r + q' holds quarter
+  // q' ^ ((r / 4) % 4) of row (or column) r; stage s adds 16 nodes
+  const float* src[LW];
+#pragma unroll
+  for (int l = 0; l < LW; ++l) {
+    int u = 256 * l + tid;
+    if (u >= SU) u = 0;
+    if (u < AU) {
+      const int r = u >> 2;
+      const int qd = (u & 3) ^ ((r >> 2) & 3);
+      src[l] = M32 + (size_t)(t.row0 + r) * NrPad + t.k0 + 4 * qd;
+    } else {
+      const int c = (u - AU) >> 2;
+      const int qd = ((u - AU) & 3) ^ ((c >> 2) & 3);
+      src[l] = B32 + (size_t)(t.col0 + c) * NrPad + t.k0 + 4 * qd;
+    }
+  }
+  const int nst = kchunk / 16;  // a multiple of 16
+
+  double accd[RBW * CBW][16];
+  f32x16 hi[RBW * CBW], lo[RBW * CBW];
+#pragma unroll
+  for (int b = 0; b < RBW * CBW; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accd[b][r] = 0.0;
+      hi[b][r] = 0.f;
+      lo[b][r] = 0.f;
+    }
+  const int rbBase = wr * RBW;
+
+  auto slot_of = [&](auto kc) -> float4* {
+    constexpr int K = decltype(kc)::value;
+    if constexpr (K == 0) return ring0;
+    else if constexpr (K == 1) return ring1;
+    else if constexpr (K == 2) return ring2;
+    else return ring3;
+  };
+  auto issue = [&](auto kc, int stage) {
+    float4* slot = slot_of(kc);
+#pragma unroll
+    for (int l = 0; l < LW; ++l)
+      __builtin_amdgcn_global_load_lds((const void*)(src[l] + (size_t)stage * 16),
+                                       (__attribute__((address_space(3))) void*)(slot + 256 * l +
+                                                                                 64 * wave),
+                                       16, 0, 0);
+  };
+  auto barrier = [&]() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  // the 8 nodes hb*8 .. hb*8 + 7 of row (or column) r of a slot region
+  auto fragment = [&](const float4* region, int r, bf16x8& t0, bf16x8& t1, bf16x8& t2) {
+    const int sw = (r >> 2) & 3;
+    const float4 a = region[4 * r + ((2 * hb) ^ sw)];
+    const float4 b = region[4 * r + ((2 * hb + 1) ^ sw)];
+    split_bf16x3(a, b, t0, t1, t2);
+  };
+  auto step = [&](auto kc, int s) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int KN = (K + NS - 1) % NS;
+    if (s + NS - 2 < nst)
+      wait_vmcnt<LW * (NS - 2)>();
+    else
+      wait_vmcnt<0>();
+    barrier();
+    if (s + NS - 1 < nst) issue(std::integral_constant<int, KN>{}, s + NS - 1);
+    const float4* slot = slot_of(kc);
+    bf16x8 bq[CBW][3];
+#pragma unroll
+    for (int cb = 0; cb < CBW; ++cb)
+      fragment(slot + AU, wc * 32 * CBW + cb * 32 + rr, bq[cb][0], bq[cb][1], bq[cb][2]);
+    bf16x8 aq[RBW][3];
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb)
+      fragment(slot, (rbBase + rb) * 32 + rr, aq[rb][0], aq[rb][1], aq[rb][2]);
+#pragma unroll
+    for (int term = 0; term < 6; ++term) {
+#pragma unroll
+      for (int rb = 0; rb < RBW; ++rb) {
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb) {
+          const int b = rb * CBW + cb;
+          switch (term) {
+            case 0: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][2], lo[b], 0, 0, 0); break;
+            case 1: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][1], lo[b], 0, 0, 0); break;
+            case 2: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[cb][0], lo[b], 0, 0, 0); break;
+            case 3: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][1], lo[b], 0, 0, 0); break;
+            case 4: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][0], lo[b], 0, 0, 0); break;
+            default: hi[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][0], hi[b], 0, 0, 0); break;
+          }
+        }
+      }
+    }
+    if (((s + 1) * 16) % kSubChunk == 0) {
+#pragma unroll
+      for (int b = 0; b < RBW * CBW; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          accd[b][r] += (double)hi[b][r] + (double)lo[b][r];
+          hi[b][r] = 0.f;
+          lo[b][r] = 0.f;
+        }
+    }
+  };
+
+  issue(std::integral_constant<int, 0>{}, 0);
+  issue(std::integral_constant<int, 1>{}, 1);
+  issue(std::integral_constant<int, 2>{}, 2);
+  for (int s0 = 0; s0 < nst; s0 += 4) {
+    step(std::integral_constant<int, 0>{}, s0);
+    step(std::integral_constant<int, 1>{}, s0 + 1);
+    step(std::integral_constant<int, 2>{}, s0 + 2);
+    step(std::integral_constant<int, 3>{}, s0 + 3);
+  }
+
+#pragma unroll
+  for (int cb = 0; cb < CBW; ++cb) {
+    const int col = t.col0 + wc * 32 * CBW + cb * 32 + rr;
+    const int j = col >> 1;
+    const int comp = col & 1;
+    if (j >= P || j >= t.pad[0]) continue;
+    const int nr = nrhoSorted[j];
+    double* dst = part + ((size_t)t.kc * lineTotal + lineOffSorted[j]) * 2 + comp;
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb) {
+      if (rbBase + rb >= t.rbN) break;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = t.row0 + (rbBase + rb) * 32 + 8 * (r >> 2) + 4 * hb + (r & 3);
+        if (row < nr) dst[(size_t)row * 2] = accd[rb * CBW + cb][r];
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // Spline coefficients (section 4.3.2).  One wave per sorted plane.  The
 // second derivatives m of the interpolating cubic spline with s'(0) = 0 and
 // s''(n-1) = 0 solve T m = d with rows
@@ -1368,10 +1560,10 @@ hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s) {
 }
 
 hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, const double* w,
-                         hipStream_t s) {
+                         bool fp32, hipStream_t s) {
   if (j1 <= j0) return hipSuccess;
   const int gy = (j1 - j0) < 65535 ? (j1 - j0) : 65535;
-  if (p.precision == 0) {
+  if (fp32) {
     dim3 grid((p.NrPad + 255) / 256, gy);
     hipLaunchKernelGGL(k_screen_f32, grid, dim3(256), 0, s, j0, j1, p.Nr, p.NrPad, p.perm, p.phi,
                        taper, w, p.B32);
@@ -1391,6 +1583,8 @@ ContractShape contract_shape(int variant) {
     case kLds64x256: return ContractShape{2, 256, 1};
     case kRing128x128: return ContractShape{4, 128, 1};
     case kRing64x256: return ContractShape{2, 256, 1};
+    case kRingF128x128: return ContractShape{4, 128, 1};
+    case kRingF64x256: return ContractShape{2, 256, 1};
     default: return ContractShape{1, 512, 1};  // kRing32x512
   }
 }
@@ -1456,6 +1650,16 @@ hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int
       case kRing64x256:
         hipLaunchKernelGGL((k_contract_bf16x6_ring<1, 4, 2, 2, 4>), g, dim3(256), 0, s, tiles,
                            p.NrPad, p.kchunk, p.P, p.lineTotal, A, B, p.nrhoSorted,
+                           p.lineOffSorted, p.part);
+        break;
+      case kRingF128x128:
+        hipLaunchKernelGGL((k_contract_bf16x6_ringf<2, 2, 2, 2>), g, dim3(256), 0, s, tiles,
+                           p.NrPad, p.kchunk, p.P, p.lineTotal, p.M32, p.B32, p.nrhoSorted,
+                           p.lineOffSorted, p.part);
+        break;
+      case kRingF64x256:
+        hipLaunchKernelGGL((k_contract_bf16x6_ringf<1, 4, 2, 2>), g, dim3(256), 0, s, tiles,
+                           p.NrPad, p.kchunk, p.P, p.lineTotal, p.M32, p.B32, p.nrhoSorted,
                            p.lineOffSorted, p.part);
         break;
       default:
