@@ -71,8 +71,9 @@ enum ContractVariant {
   kRing128x128 = 4,
   kRing64x256 = 5,
   kRing32x512 = 6,
-  // split-BF16 only: the same ring fed with FP32 M and FP32 screen columns,
-  // split into BF16 terms in registers (two thirds of the operand bytes)
+  // the same ring fed with FP32 M and FP32 screen columns: split into BF16
+  // terms in registers (split-BF16, two thirds of the operand bytes) or
+  // multiplied on the FP32 matrix cores (FP32)
   kRingF128x128 = 7,
   kRingF64x256 = 8,
   kNumVariants = 9
@@ -85,9 +86,9 @@ struct ContractShape {
   int pad;
 };
 ContractShape contract_shape(int variant);
-// The ring variants exist for the split-BF16 contraction only.
+// The BF16-term ring variants exist for the split-BF16 contraction only.
 inline bool variant_supported(int precision, int variant) {
-  return variant < kRing128x128 || precision == 1;
+  return variant < kRing128x128 || variant >= kRingF128x128 || precision == 1;
 }
 // Whether a variant reads the FP32 screen (B32) rather than its BF16 terms.
 inline bool variant_fp32_screen(int precision, int variant) {

@@ -1017,6 +1017,193 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_ringf(
 }
 
 // --------------------------------------------------------------------------
+// FP32 contraction through the same FP32 ring: v_mfma_f32_32x32x2f32, FP32
+// sums over kSubChunk nodes added to FP64 running sums.
+// --------------------------------------------------------------------------
+template <int WR, int WC, int RBW, int CBW, int NS>
+__global__ __launch_bounds__(256) void k_contract_f32_ringf(
+    const Tile* __restrict__ tiles, int NrPad, int kchunk, int P, int lineTotal,
+    const float* __restrict__ M32, const float* __restrict__ B32,
+    const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
+    double* __restrict__ part) {
+  constexpr int BM = 32 * RBW * WR;
+  constexpr int BN = 32 * CBW * WC;
+  constexpr int AU = BM * 4;                // 16-byte quarters of M per stage
+  constexpr int SU = AU + BN * 4;           // quarters per stage
+  constexpr int LW = (SU + 255) / 256;      // load instructions per wave per stage
+  constexpr int SLOT = LW * 256;
+  static_assert(LW * (NS - 2) < 64, "too many loads in flight for vmcnt");
+  static_assert(NS == 4 || NS == 8, "ring depth");
+  __shared__ float4 ring0[SLOT];
+  __shared__ float4 ring1[SLOT];
+  __shared__ float4 ring2[SLOT];
+  __shared__ float4 ring3[SLOT];
+  __shared__ float4 ring4[NS > 4 ? SLOT : 1];
+  __shared__ float4 ring5[NS > 4 ? SLOT : 1];
+  __shared__ float4 ring6[NS > 4 ? SLOT : 1];
+  __shared__ float4 ring7[NS > 4 ? SLOT : 1];
+
+  const Tile t = tiles[blockIdx.x];
+  if (t.row0 < 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave / WC;
+  const int wc = wave - wr * WC;
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+
+  // source of slot position u = 256 l + tid: position 4 r + q' holds quarter
+  // q' ^ ((r / 4) % 4) of row (or column) r; stage s adds 16 nodes
+  const float* src[LW];
+#pragma unroll
+  for (int l = 0; l < LW; ++l) {
+    int u = 256 * l + tid;
+    if (u >= SU) u = 0;
+    if (u < AU) {
+      const int r = u >> 2;
+      const int qd = (u & 3) ^ ((r >> 2) & 3);
+      src[l] = M32 + (size_t)(t.row0 + r) * NrPad + t.k0 + 4 * qd;
+    } else {
+      const int c = (u - AU) >> 2;
+      const int qd = ((u - AU) & 3) ^ ((c >> 2) & 3);
+      src[l] = B32 + (size_t)(t.col0 + c) * NrPad + t.k0 + 4 * qd;
+    }
+  }
+  const int nst = kchunk / 16;  // a multiple of 16
+
+  double accd[RBW * CBW][16];
+  f32x16 hi[RBW * CBW];
+#pragma unroll
+  for (int b = 0; b < RBW * CBW; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accd[b][r] = 0.0;
+      hi[b][r] = 0.f;
+    }
+  const int rbBase = wr * RBW;
+
+  auto slot_of = [&](auto kc) -> float4* {
+    constexpr int K = decltype(kc)::value;
+    if constexpr (K == 0) return ring0;
+    else if constexpr (K == 1) return ring1;
+    else if constexpr (K == 2) return ring2;
+    else if constexpr (K == 3) return ring3;
+    else if constexpr (K == 4) return ring4;
+    else if constexpr (K == 5) return ring5;
+    else if constexpr (K == 6) return ring6;
+    else return ring7;
+  };
+  auto issue = [&](auto kc, int stage) {
+    float4* slot = slot_of(kc);
+#pragma unroll
+    for (int l = 0; l < LW; ++l)
+      __builtin_amdgcn_global_load_lds((const void*)(src[l] + (size_t)stage * 16),
+                                       (__attribute__((address_space(3))) void*)(slot + 256 * l +
+                                                                                 64 * wave),
+                                       16, 0, 0);
+  };
+  auto barrier = [&]() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  // the 8 nodes hb*8 .. hb*8 + 7 of row (or column) r of a slot region
+  auto fragment = [&](const float4* region, int r, float4& lo4, float4& hi4) {
+    const int sw = (r >> 2) & 3;
+    lo4 = region[4 * r + ((2 * hb) ^ sw)];
+    hi4 = region[4 * r + ((2 * hb + 1) ^ sw)];
+  };
+  auto step = [&](auto kc, int s) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int KN = (K + NS - 1) % NS;
+    if (s + NS - 2 < nst)
+      wait_vmcnt<LW * (NS - 2)>();
+    else
+      wait_vmcnt<0>();
+    barrier();
+    if (s + NS - 1 < nst) issue(std::integral_constant<int, KN>{}, s + NS - 1);
+    const float4* slot = slot_of(kc);
+    float bq[CBW][8];
+#pragma unroll
+    for (int cb = 0; cb < CBW; ++cb) {
+      float4 a, b;
+      fragment(slot + AU, wc * 32 * CBW + cb * 32 + rr, a, b);
+      bq[cb][0] = a.x; bq[cb][1] = a.y; bq[cb][2] = a.z; bq[cb][3] = a.w;
+      bq[cb][4] = b.x; bq[cb][5] = b.y; bq[cb][6] = b.z; bq[cb][7] = b.w;
+    }
+    float aq[RBW][8];
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb) {
+      float4 a, b;
+      fragment(slot, (rbBase + rb) * 32 + rr, a, b);
+      aq[rb][0] = a.x; aq[rb][1] = a.y; aq[rb][2] = a.z; aq[rb][3] = a.w;
+      aq[rb][4] = b.x; aq[rb][5] = b.y; aq[rb][6] = b.z; aq[rb][7] = b.w;
+    }
+    // K-step kk pairs node kk (lanes 0-31) with node 8 + kk (lanes 32-63), in
+    // A and B alike, so the 8 steps cover the stage's 16 nodes
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+      for (int rb = 0; rb < RBW; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+          hi[rb * CBW + cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[rb][kk], bq[cb][kk],
+                                                                   hi[rb * CBW + cb], 0, 0, 0);
+    if (((s + 1) * 16) % kSubChunk == 0) {
+#pragma unroll
+      for (int b = 0; b < RBW * CBW; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          accd[b][r] += (double)hi[b][r];
+          hi[b][r] = 0.f;
+        }
+    }
+  };
+
+  issue(std::integral_constant<int, 0>{}, 0);
+  issue(std::integral_constant<int, 1>{}, 1);
+  issue(std::integral_constant<int, 2>{}, 2);
+  if constexpr (NS == 8) {
+    issue(std::integral_constant<int, 3>{}, 3);
+    issue(std::integral_constant<int, 4>{}, 4);
+    issue(std::integral_constant<int, 5>{}, 5);
+    issue(std::integral_constant<int, 6>{}, 6);
+  }
+  for (int s0 = 0; s0 < nst; s0 += NS) {
+    step(std::integral_constant<int, 0>{}, s0);
+    step(std::integral_constant<int, 1>{}, s0 + 1);
+    step(std::integral_constant<int, 2>{}, s0 + 2);
+    step(std::integral_constant<int, 3>{}, s0 + 3);
+    if constexpr (NS == 8) {
+      step(std::integral_constant<int, 4>{}, s0 + 4);
+      step(std::integral_constant<int, 5>{}, s0 + 5);
+      step(std::integral_constant<int, 6>{}, s0 + 6);
+      step(std::integral_constant<int, 7>{}, s0 + 7);
+    }
+  }
+
+#pragma unroll
+  for (int cb = 0; cb < CBW; ++cb) {
+    const int col = t.col0 + wc * 32 * CBW + cb * 32 + rr;
+    const int j = col >> 1;
+    const int comp = col & 1;
+    if (j >= P || j >= t.pad[0]) continue;
+    const int nr = nrhoSorted[j];
+    double* dst = part + ((size_t)t.kc * lineTotal + lineOffSorted[j]) * 2 + comp;
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb) {
+      if (rbBase + rb >= t.rbN) break;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = t.row0 + (rbBase + rb) * 32 + 8 * (r >> 2) + 4 * hb + (r & 3);
+        if (row < nr) dst[(size_t)row * 2] = accd[rb * CBW + cb][r];
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // Spline coefficients (section 4.3.2).  One wave per sorted plane.  The
 // second derivatives m of the interpolating cubic spline with s'(0) = 0 and
 // s''(n-1) = 0 solve T m = d with rows
@@ -1619,6 +1806,16 @@ hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int
     const float4* A = (const float4*)p.M32;
     const float4* B = (const float4*)p.B32;
     switch (variant) {
+      case kRingF128x128:
+        hipLaunchKernelGGL((k_contract_f32_ringf<2, 2, 2, 2, 8>), g, dim3(256), 0, s, tiles,
+                           p.NrPad, p.kchunk, p.P, p.lineTotal, p.M32, p.B32, p.nrhoSorted,
+                           p.lineOffSorted, p.part);
+        break;
+      case kRingF64x256:
+        hipLaunchKernelGGL((k_contract_f32_ringf<1, 4, 2, 2, 8>), g, dim3(256), 0, s, tiles,
+                           p.NrPad, p.kchunk, p.P, p.lineTotal, p.M32, p.B32, p.nrhoSorted,
+                           p.lineOffSorted, p.part);
+        break;
       case kWave32x64:
         hipLaunchKernelGGL(k_contract_f32<2>, g, dim3(64), 0, s, tiles, p.NrPad, p.kchunk, p.P,
                            p.lineTotal, p.M32, p.B32, p.nrhoSorted, p.lineOffSorted, p.part);
