@@ -259,6 +259,41 @@ def _gridding_paths(steps):
     return res
 
 
+def _gradient_path(steps):
+    """Differentiation workload (256 planes of 2048 free taper samples, S 127,
+    os 4): one forward generate and one adjoint (dL/dtaper, dL/dw from a
+    dL/dcache of the cache's size), split-BF16 forward, FP64 adjoint."""
+    import torch
+    import workloads as W
+    from paper_1904_08463_amd import Plan
+    wl = W.grad()
+    plan = Plan.from_workload(wl, precision="bf16x6")
+    taper = torch.from_numpy(wl.taper).cuda()
+    w = torch.from_numpy(wl.w).cuda()
+    out = plan.generate(taper, w)
+    g_out = torch.randn(out.shape, dtype=torch.complex64, device="cuda")
+    g_tau = torch.empty(wl.n_radial, dtype=torch.float32, device="cuda")
+    g_w = torch.empty(wl.n_planes, dtype=torch.float64, device="cuda")
+    plan.grad(taper, w, g_out, g_tau, g_w)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd = bwd = 0.0
+    for _ in range(steps):
+        e[0].record()
+        plan.generate(taper, w, out)
+        e[1].record()
+        plan.grad(taper, w, g_out, g_tau, g_w)
+        e[2].record()
+        torch.cuda.synchronize()
+        fwd += e[0].elapsed_time(e[1])
+        bwd += e[1].elapsed_time(e[2])
+    nbytes = out.numel() * 8
+    plan.close()
+    return {"forward_ms": fwd / steps, "adjoint_ms": bwd / steps, "cache_bytes": int(nbytes),
+            "adjoint_read_GBs": nbytes / (bwd / steps * 1e-3) / 1e9, "n_planes": wl.n_planes,
+            "n_radial": wl.n_radial}
+
+
 def _wpartition_paths(steps):
     """w-plane partition (sort by |w|, equal-size planes, mean |w|): the
     paper-shaped record set (505440 records, 128 planes) and the same records
@@ -398,6 +433,7 @@ def main():
         paths.update(_projslice_paths(wl, taper, w, out, args.steps))
     paths["wpartition"] = _wpartition_paths(args.steps)
     paths["gridding_paper_setting"] = _gridding_paths(args.steps)
+    paths["gradient"] = _gradient_path(args.steps)
 
     line = {
         "metric": "w-kernels/sec at <=1e-6 rel err (split-BF16 Hankel; FP32 Hankel beside it)",

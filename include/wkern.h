@@ -221,6 +221,7 @@ wkern_status wkern_prepare_lines(wkern_plan_t plan, const float* taper, const do
  * grid_size:    N, even.
  * grid:         device complex64 [N][N], accumulated into (the caller clears
  *               it); FP32 atomic sums, so the last bits depend on timing.
+ * n_records = 0 is a no-op (the record pointers may then be NULL).
  * Asynchronous on `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 wkern_status wkern_grid(wkern_plan_t plan, const double* u, const double* v, const double* w,
                         const void* vis, int64_t n_records, const int32_t* order,

@@ -898,14 +898,14 @@ wkern_status wkern_grid(wkern_plan_t plan, const double* u, const double* v, con
                         void* stream) {
   clear_error();
   if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
-  if (!u || !v || !w || !vis || !order || !plane_start || !support || !grid)
-    return fail(WKERN_ERR_INVALID_ARG, "NULL argument");
-  if (cache && !cache_offsets) return fail(WKERN_ERR_INVALID_ARG, "cache_offsets is NULL");
   if (n_records < 0 || n_records > 0x7FFFFFFF)
     return fail(WKERN_ERR_INVALID_ARG, "n_records %lld out of range", (long long)n_records);
   if (grid_size < 2 || grid_size > 65536 || grid_size % 2)
     return fail(WKERN_ERR_INVALID_ARG, "grid_size %d must be even, 2 .. 65536", grid_size);
-  if (n_records == 0) return WKERN_OK;
+  if (n_records == 0) return WKERN_OK;  // nothing is read or written
+  if (!u || !v || !w || !vis || !order || !plane_start || !support || !grid)
+    return fail(WKERN_ERR_INVALID_ARG, "NULL argument");
+  if (cache && !cache_offsets) return fail(WKERN_ERR_INVALID_ARG, "cache_offsets is NULL");
   DeviceGuard guard(plan->desc.device);
   wkern_status s;
   if (!plan->gridChunks &&

@@ -146,3 +146,34 @@ def test_grid_rejects_bad_arguments():
     with pytest.raises(WkernError):
         plan.prepare_lines(_dev(wl.taper), _dev(wl.w), frac=1.0)
     plan.close()
+
+
+def test_grid_empty_and_outside_records():
+    """No records: nothing happens.  Records whose footprint lies wholly or
+    partly off the grid: only the cells inside are touched (G3)."""
+    from paper_1904_08463_amd import Plan, wpartition
+    gw = W.grid_small(4, n_rec=40, n_planes=2)
+    n = gw.grid_size
+    du = 1.0 / (gw.image_size * gw.cellsize)
+    # push half the records near or beyond the grid edge
+    u = gw.u.copy()
+    u[::2] = (0.5 * n + np.linspace(-3, 8, u[::2].size)) * du
+    gw.u = u
+    sup = np.array([15, 9])
+    order_d, start_d, wp_d = wpartition(_dev(gw.w), 2)
+    order, start, wp = P.partition(gw.w, 2)
+    caches, _ = H.generate(gw.image_size, gw.cellsize, gw.n_radial, gw.oversampling, gw.taper,
+                           wp, sup)
+    ref = G.grid(gw.u, gw.v, gw.w, gw.vis, order, start, caches, sup, gw.oversampling, n, du)
+    a, e = _bounds(gw, order, start, caches, sup, du, n)
+    plan = Plan(gw.image_size, gw.cellsize, gw.n_radial, gw.oversampling, sup, gw.max_support)
+    sup_d = plan.prepare_lines(_dev(gw.taper), wp_d)
+    g = torch.zeros((n, n), dtype=torch.complex64, device="cuda")
+    empty = torch.empty(0, dtype=torch.float64, device="cuda")
+    plan.grid(empty, empty, empty, torch.empty(0, dtype=torch.complex64, device="cuda"),
+              torch.empty(0, dtype=torch.int32, device="cuda"),
+              torch.zeros(3, dtype=torch.int64, device="cuda"), sup_d, g)
+    assert g.abs().max().item() == 0.0
+    plan.grid(_dev(gw.u), _dev(gw.v), _dev(gw.w), _dev(gw.vis), order_d, start_d, sup_d, g)
+    _check(g.cpu().numpy(), ref, a, e, 1e-5, "edge records")
+    plan.close()

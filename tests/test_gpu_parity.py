@@ -275,3 +275,16 @@ def test_mirrored_planes(precision):
                               np.conj(a[plan.offsets[q]:plan.offsets[q + 1]]))
         assert np.array_equal(lines[offs[p]:offs[p + 1]], np.conj(lines[offs[q]:offs[q + 1]]))
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_longest_radial_line(precision):
+    """The largest radial line the plan accepts (2048 nodes: spline LDS of
+    96 KB, resample LDS of 64 KB): S = 255 at os 8 with q = 2 gives 2036
+    nodes; a short plane rides along in the same batch."""
+    wl = W.paper(n_planes=2)
+    wl.w = np.array([19000.0, 300.0])
+    wl.support = np.array([255, 9], dtype=np.int32)
+    wl.max_support = 255
+    wl.radial_refine = 2
+    _run_full(wl, precision)
