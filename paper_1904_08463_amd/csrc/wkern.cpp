@@ -1066,8 +1066,6 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
     if ((s = plan->alloc(&gs.mom, (size_t)g.lineTotalAll * 4, "adjoint moments")) != WKERN_OK)
       return s;
     if ((s = plan->alloc(&gs.gy, lt, "adjoint lines")) != WKERN_OK) return s;
-    if ((s = plan->alloc(&gs.gm, lt, "adjoint lines")) != WKERN_OK) return s;
-    if ((s = plan->alloc(&gs.dp, lt, "adjoint lines")) != WKERN_OK) return s;
     const size_t pn = (size_t)g.P * g.NrPad;
     if ((s = plan->alloc(&gs.ure, pn, "adjoint screen")) != WKERN_OK) return s;
     if ((s = plan->alloc(&gs.wterm, pn, "adjoint screen")) != WKERN_OK) return s;

@@ -134,8 +134,6 @@ struct DevPlan {
 struct GradScratch {
   double2* mom;   // [lineTotal][4] coefficient moments
   double2* gy;    // [lineTotal] gradient of the radial lines
-  double2* gm;    // [lineTotal] gradient of the second derivatives / Thomas table
-  double2* dp;    // [lineTotal] Thomas right-hand side / solution
   double* ure;    // [P][NrPad] Re u
   double* wterm;  // [P][NrPad] 2 pi phi tau Im u
 };

@@ -1478,115 +1478,139 @@ __global__ __launch_bounds__(kMomThreads) void k_resample_T(
 // Resample transpose, part 2: coefficient moments -> gradient of the radial
 // line.  c0 = y_k, c1 = y_{k+1} - y_k - m_k/3 - m_{k+1}/6, c2 = m_k/2,
 // c3 = (m_{k+1} - m_k)/6 give dL/dy and dL/dm; the second derivatives are
-// m = T^-1 D y, so dL/dy += D^T T^-T dL/dm, with T^T solved by Thomas
-// elimination.  One thread per sorted plane (complex arithmetic, real
-// coefficients).  gy, z and dp are FP64 complex scratch of the line layout.
-__global__ void k_spline_T(int P, int interp, const int32_t* __restrict__ perm,
-                           const int32_t* __restrict__ nrhoSorted,
-                           const int32_t* __restrict__ lineOffSorted,
-                           const int32_t* __restrict__ lineOffCaller,
-                           const int32_t* __restrict__ mirStart,
-                           const int32_t* __restrict__ mirList,
-                           const double2* __restrict__ mom, double2* __restrict__ gy,
-                           double2* __restrict__ gm, double2* __restrict__ dp) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= P) return;
+// m = T^-1 D y, so dL/dy += D^T T^-T dL/dm.  T^T has the rows [2 1],
+// [1 4 1] ... [1 4 0], [1 1], so its Thomas factors are the forward spline's
+// c'_k up to row n - 3, c'_{n-2} = 0, and a last pivot of 1.  One wave per
+// sorted plane, the line in LDS; like the forward spline, every lane runs the
+// elimination and the back substitution over its own segment from
+// kSplineWarm nodes outside it with a zero start value (damped by c'_k ~
+// 0.27 per node), exact at the two ends of the line.  Mirrored planes add
+// their moments to their source's, in a fixed order.
+__global__ __launch_bounds__(64) void k_spline_T(int j0, int interp,
+                                                 const int32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ nrhoSorted,
+                                                 const int32_t* __restrict__ lineOffSorted,
+                                                 const int32_t* __restrict__ lineOffCaller,
+                                                 const int32_t* __restrict__ mirStart,
+                                                 const int32_t* __restrict__ mirList,
+                                                 const double* __restrict__ cprime,
+                                                 const double2* __restrict__ mom,
+                                                 double2* __restrict__ gy) {
+  extern __shared__ double2 smT[];
+  const int j = j0 + blockIdx.x;
+  const int lane = threadIdx.x;
   const int n = nrhoSorted[j];
-  const size_t off = lineOffSorted[j];
   const double2* M = mom + (size_t)lineOffCaller[perm[j]] * 4;
-  const int m0 = mirStart[j], m1 = mirStart[j + 1];
-  double2* y = gy + off;
-  double2* m = gm + off;
-  double2* d = dp + off;
-  for (int k = 0; k < n; ++k) {
-    y[k] = make_double2(0, 0);
-    m[k] = make_double2(0, 0);
-  }
-  for (int k = 0; k < n; ++k) {
-    double2 g0 = M[4 * k], g1 = M[4 * k + 1], g2 = M[4 * k + 2], g3 = M[4 * k + 3];
-    for (int mi = m0; mi < m1; ++mi) {  // mirrored planes of this source
+  const int mi0 = mirStart[j], mi1 = mirStart[j + 1];
+  double2* y = smT;          // [n] dL/dy
+  double2* m = smT + n;      // [n] dL/dm, then the eliminated d'
+  double2* z = smT + 2 * n;  // [n] T^-T dL/dm
+  // moments of interval k, mirrored planes added in a fixed order
+  auto moments = [&](int k, double2 (&g)[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) g[t] = M[4 * k + t];
+    for (int mi = mi0; mi < mi1; ++mi) {
       const double2* Mm = mom + (size_t)lineOffCaller[mirList[mi]] * 4;
-      g0.x += Mm[4 * k].x;
-      g0.y += Mm[4 * k].y;
-      g1.x += Mm[4 * k + 1].x;
-      g1.y += Mm[4 * k + 1].y;
-      g2.x += Mm[4 * k + 2].x;
-      g2.y += Mm[4 * k + 2].y;
-      g3.x += Mm[4 * k + 3].x;
-      g3.y += Mm[4 * k + 3].y;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        g[t].x += Mm[4 * k + t].x;
+        g[t].y += Mm[4 * k + t].y;
+      }
     }
+  };
+  for (int k = lane; k < n; k += 64) {
+    double2 yk = make_double2(0.0, 0.0), mk = make_double2(0.0, 0.0);
+    double2 g[4];
+    if (k >= 1) {  // from interval k - 1 (every interval below n - 1 has a cubic)
+      moments(k - 1, g);
+      yk.x += g[1].x;
+      yk.y += g[1].y;
+      if (interp == 1) {
+        mk.x += -g[1].x / 6.0 + g[3].x / 6.0;
+        mk.y += -g[1].y / 6.0 + g[3].y / 6.0;
+      }
+    }
+    moments(k, g);
     if (k == n - 1) {  // the last node's interval is the constant y_{n-1}
-      y[k].x += g0.x;
-      y[k].y += g0.y;
-      continue;
-    }
-    if (interp == 1) {
-      y[k].x += g0.x - g1.x;
-      y[k].y += g0.y - g1.y;
-      y[k + 1].x += g1.x;
-      y[k + 1].y += g1.y;
-      m[k].x += -g1.x / 3.0 + 0.5 * g2.x - g3.x / 6.0;
-      m[k].y += -g1.y / 3.0 + 0.5 * g2.y - g3.y / 6.0;
-      m[k + 1].x += -g1.x / 6.0 + g3.x / 6.0;
-      m[k + 1].y += -g1.y / 6.0 + g3.y / 6.0;
+      yk.x += g[0].x;
+      yk.y += g[0].y;
     } else {
-      y[k].x += g0.x - g1.x;
-      y[k].y += g0.y - g1.y;
-      y[k + 1].x += g1.x;
-      y[k + 1].y += g1.y;
+      yk.x += g[0].x - g[1].x;
+      yk.y += g[0].y - g[1].y;
+      if (interp == 1) {
+        mk.x += -g[1].x / 3.0 + 0.5 * g[2].x - g[3].x / 6.0;
+        mk.y += -g[1].y / 3.0 + 0.5 * g[2].y - g[3].y / 6.0;
+      }
     }
+    y[k] = yk;
+    m[k] = mk;
   }
-  if (interp != 1) return;
-  // T^T rows: 0: [2, 1]; 1..n-3: [1, 4, 1]; n-2: [1, 4, 0]; n-1: [1, 1]
-  // (T: row 0 [2 1], interior [1 4 1], last row m_{n-1} = 0).
-  double cp = 0.5;  // c'_0
-  d[0] = make_double2(m[0].x * 0.5, m[0].y * 0.5);
-  double cprev = cp;
-  // store c'_k in the real slot of a second pass: recompute on the way back
-  for (int k = 1; k < n; ++k) {
-    const double a = 1.0;
-    const double b = (k == n - 1) ? 1.0 : 4.0;
-    const double c = (k >= n - 2) ? 0.0 : 1.0;
-    const double den = b - a * cprev;
-    d[k].x = (m[k].x - a * d[k - 1].x) / den;
-    d[k].y = (m[k].y - a * d[k - 1].y) / den;
-    cprev = c / den;
-  }
-  // back substitution needs c'_k again: recompute forward coefficients lazily
-  // by storing them in m (no longer needed)
-  cprev = 0.5;
-  m[0] = make_double2(0.5, 0.0);
-  for (int k = 1; k < n; ++k) {
-    const double b = (k == n - 1) ? 1.0 : 4.0;
-    const double c = (k >= n - 2) ? 0.0 : 1.0;
-    const double den = b - cprev;
-    cprev = c / den;
-    m[k] = make_double2(cprev, 0.0);
-  }
-  // z_{n-1} = d'_{n-1}; z_k = d'_k - c'_k z_{k+1}  (z overwrites d)
-  for (int k = n - 2; k >= 0; --k) {
-    d[k].x -= m[k].x * d[k + 1].x;
-    d[k].y -= m[k].x * d[k + 1].y;
-  }
-  // y += D^T z: D rows 0: [-6, 6]; k = 1..n-2: [6, -12, 6]; n-1: 0
-  for (int i = 0; i < n; ++i) {
-    double ax = 0.0, ay = 0.0;
-    if (i >= 1 && i - 1 <= n - 2) {
-      ax += 6.0 * d[i - 1].x;
-      ay += 6.0 * d[i - 1].y;
+  __syncthreads();
+  if (interp == 1) {
+    const int L = (n + 63) / 64;
+    const int s0 = min(lane * L, n);
+    const int e0 = min(s0 + L, n);
+    // elimination, rows 0 .. n-1, over [start, e0) with a zero start value
+    {
+      const int start = max(0, s0 - kSplineWarm);
+      double2 prev = make_double2(0.0, 0.0);
+      for (int k = start; k < e0; ++k) {
+        double2 v;
+        if (k == 0) {
+          v.x = 0.5 * m[0].x;
+          v.y = 0.5 * m[0].y;
+        } else if (k == n - 1) {
+          v.x = m[k].x - prev.x;
+          v.y = m[k].y - prev.y;
+        } else {
+          v.x = (m[k].x - prev.x) * cprime[k];
+          v.y = (m[k].y - prev.y) * cprime[k];
+        }
+        prev = v;
+        if (k >= s0) z[k] = v;  // z holds d' until the back substitution
+      }
     }
-    if (i <= n - 2) {
-      const double dd = i == 0 ? -6.0 : -12.0;
-      ax += dd * d[i].x;
-      ay += dd * d[i].y;
+    __syncthreads();
+    for (int k = s0; k < e0; ++k) m[k] = z[k];  // d'
+    __syncthreads();
+    // back substitution z_k = d'_k - c'_k z_{k+1} (c'_{n-2} = 0, z_{n-1} = d'_{n-1})
+    {
+      const int top = min(n - 1, e0 - 1 + kSplineWarm);
+      double2 next = make_double2(0.0, 0.0);
+      for (int k = top; k >= s0; --k) {
+        double2 v = m[k];
+        if (k <= n - 3) {
+          v.x -= cprime[k] * next.x;
+          v.y -= cprime[k] * next.y;
+        }
+        next = v;
+        if (k < e0) z[k] = v;
+      }
     }
-    if (i + 1 >= 1 && i + 1 <= n - 2) {
-      ax += 6.0 * d[i + 1].x;
-      ay += 6.0 * d[i + 1].y;
+    __syncthreads();
+    // y += D^T z: D rows 0: [-6, 6]; k = 1..n-2: [6, -12, 6]; n-1: 0
+    for (int i = lane; i < n; i += 64) {
+      double ax = 0.0, ay = 0.0;
+      if (i >= 1 && i - 1 <= n - 2) {
+        ax += 6.0 * z[i - 1].x;
+        ay += 6.0 * z[i - 1].y;
+      }
+      if (i <= n - 2) {
+        const double dd = i == 0 ? -6.0 : -12.0;
+        ax += dd * z[i].x;
+        ay += dd * z[i].y;
+      }
+      if (i + 1 >= 1 && i + 1 <= n - 2) {
+        ax += 6.0 * z[i + 1].x;
+        ay += 6.0 * z[i + 1].y;
+      }
+      y[i].x += ax;
+      y[i].y += ay;
     }
-    y[i].x += ax;
-    y[i].y += ay;
+    __syncthreads();
   }
+  double2* out = gy + lineOffSorted[j];
+  for (int k = lane; k < n; k += 64) out[k] = y[k];
 }
 
 // Transposed Hankel contraction and screen backward:
@@ -1970,9 +1994,15 @@ hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* tap
                      (const float2*)gout, gs.mom);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_spline_T, dim3((p.P + 63) / 64), dim3(64), 0, s, p.P, p.interp, p.perm,
+  const size_t shmT = (size_t)3 * p.nrhoMax * sizeof(double2);
+  if (shmT > 65536) {
+    e = hipFuncSetAttribute((const void*)k_spline_T, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmT);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_spline_T, dim3(p.P), dim3(64), shmT, s, 0, p.interp, p.perm,
                      p.nrhoSorted, p.lineOffSorted, p.lineOffCaller, p.mirStart, p.mirList,
-                     gs.mom, gs.gy, gs.gm, gs.dp);
+                     p.cprime, gs.mom, gs.gy);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   dim3 g3((p.Nr + 255) / 256, p.P);
   hipLaunchKernelGGL(k_contract_T, g3, dim3(256), 0, s, p.Nr, p.NrPad, p.perm, p.nrhoSorted,
