@@ -34,7 +34,7 @@ MFMA_PEAK_TFLOPS = {"bf16x6": 2500.0, "fp32": 157.3}  # dense BF16 / FP32 matrix
 COUNTERS = os.path.join(ROOT, "profiles", "k_resample_batch_counters.txt")
 RESAMPLE_SOURCES = ("paper_1904_08463_amd/csrc/wkern_resample.hip",
                     "paper_1904_08463_amd/csrc/wkern_radial.h",
-                    "paper_1904_08463_amd/csrc/wkern_internal.h")
+                    "paper_1904_08463_amd/csrc/wkern_tables.h")
 
 
 def _parse():

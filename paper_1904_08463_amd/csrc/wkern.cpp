@@ -1069,6 +1069,9 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
     const size_t pn = (size_t)g.P * g.NrPad;
     if ((s = plan->alloc(&gs.ure, pn, "adjoint screen")) != WKERN_OK) return s;
     if ((s = plan->alloc(&gs.wterm, pn, "adjoint screen")) != WKERN_OK) return s;
+    if ((s = plan->alloc(&gs.momfx, (size_t)g.lineTotalAll * 8, "adjoint moments")) != WKERN_OK)
+      return s;
+    if ((s = plan->alloc(&gs.amax, (size_t)g.Pall, "adjoint maxima")) != WKERN_OK) return s;
     plan->gradReady = true;
   }
   WK_HIP(launch_grad(g, plan->grad, taper, w, grad_out, grad_taper, grad_w, (hipStream_t)stream),

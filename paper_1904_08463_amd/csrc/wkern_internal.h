@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wkern_tables.h"
+
 namespace wkern {
 
 // Sets the calling thread's detail string returned by wkern_last_error().
@@ -26,27 +28,6 @@ constexpr int kNumXcd = 8;
 // Warm-up length of the truncated spline recurrences; the neglected start
 // value is damped by (2 - sqrt 3)^32 ~ 5e-19.
 constexpr int kSplineWarm = 32;
-
-// Per-plane table used by the resampler (caller order).
-struct PlaneInfo {
-  int64_t out_off;    // complex64 offset of the plane's cache
-  int32_t line_off;   // offset of its (or its source plane's) radial line, sorted order
-  int32_t nrho;       // radial nodes
-  int32_t S;          // full width
-  int32_t h;          // half width
-  int32_t lim;        // (os h)^2
-  float invS;         // 1 / S (estimate for the exact small division)
-  int32_t conj;       // 1: mirrored plane, written as the conjugate of its source
-  int32_t line_off_caller;  // offset of its own line in the caller-order layout
-};
-
-// One block of output elements [e0, e1) of plane p (plane-local indices).
-struct ResampleUnit {
-  int32_t p;
-  int32_t e0;
-  int32_t e1;
-  int32_t pad;
-};
 
 // One contraction tile: rows [row0, row0 + rows), sorted columns
 // [col0, col0 + cols), radial nodes [k0, k0 + kchunk).  row0 < 0 marks a
@@ -136,6 +117,8 @@ struct GradScratch {
   double2* gy;    // [lineTotal] gradient of the radial lines
   double* ure;    // [P][NrPad] Re u
   double* wterm;  // [P][NrPad] 2 pi phi tau Im u
+  unsigned long long* momfx;  // [lineTotalAll][8] fixed-point moments
+  uint32_t* amax;             // [Pall] max |G| per plane (FP32 bits)
 };
 
 hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* taper,

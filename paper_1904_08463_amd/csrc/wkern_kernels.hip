@@ -10,6 +10,7 @@
 //   k_spline       spline coefficients of each radial line (section 4.3.2);
 //   k_resample     oversampled 2D kernels over the circular support
 //                  (section 4.4, Algorithm 2), in wkern_resample.hip.
+#include <cmath>
 #include <type_traits>
 
 #include "wkern_internal.h"
@@ -1363,115 +1364,196 @@ __global__ void k_lines_out(int Pall, int nkc, int lineTotal, const PlaneInfo* _
 // its source's, so its gradient enters conjugated): for interval k of plane
 // p the moments
 //   g_j[k] = sum over cache samples e with interval(e) = k of u(e)^j G(e),
-// j = 0..3 (the gradients of the power-form coefficients c0..c3).  One
-// thread owns (k, fv, fu) and visits the rows b whose |Y| can reach the
-// interval, and in each row the two runs of a whose radius can; the sample
-// is counted only if the forward's own radial_pos assigns it to k, so this
-// is exactly the transpose of what the forward evaluated.  The os^2 partial
-// moments of an interval are then summed in (fv, fu) order.
+// j = 0..3 (the gradients of the power-form coefficients c0..c3).
+//
+// One thread per sample, over the resample units (coalesced reads): the
+// sample's interval and fraction come from the forward's own radial_pos, so
+// this is exactly the transpose of what the forward evaluated.  Each product
+// u^j G is formed in FP64 and added as a 64-bit fixed-point integer, first
+// into the workgroup's LDS bins and then into the global bins: integer sums
+// do not depend on the order of the additions, so the result is
+// bit-reproducible without a fixed reduction order.  The fixed-point scale of
+// plane p is 2^E_p with E_p = 60 - eN - e_p, where max |G| < 2^e_p (a
+// pre-pass) and 2^eN bounds the samples of one interval: every sum stays
+// below 2^60 and the quantum is at most 2^(eN - 59) max |G| (about 1e-13 of
+// it for eN = 16), well inside what FP64 accumulation of the same products
+// keeps.  A plane whose G holds a non-finite value gets NaN moments.
 constexpr int kMomThreads = 256;
 
+__device__ __forceinline__ int moment_exponent(uint32_t amaxBits, int eN) {
+  int e = 0;
+  (void)frexpf(__uint_as_float(amaxBits), &e);  // 0 for max |G| = 0
+  return 60 - eN - e;
+}
+
+// Zeroes the fixed-point bins [n8] and the per-plane maxima [P].
+__global__ void k_grad_clear(int64_t n8, unsigned long long* __restrict__ fx, int P,
+                             uint32_t* __restrict__ amax) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = i; j < n8; j += stride) fx[j] = 0ull;
+  for (int64_t j = i; j < P; j += stride) amax[j] = 0u;
+}
+
+// Per-plane max |Re G|, |Im G| as FP32 bits (a non-finite value counts as
+// +inf); max is order independent.
+__global__ __launch_bounds__(256) void k_grad_absmax(const ResampleUnit* __restrict__ units,
+                                                     const PlaneInfo* __restrict__ planes,
+                                                     const float2* __restrict__ g,
+                                                     uint32_t* __restrict__ amax) {
+  __shared__ float red[4];
+  const ResampleUnit u = units[blockIdx.x];
+  const float2* gp = g + planes[u.p].out_off;
+  float m = 0.f;
+  auto take = [&](float2 v) {
+    const float a = fmaxf(fabsf(v.x), fabsf(v.y));
+    m = fmaxf(m, (isfinite(v.x) && isfinite(v.y)) ? a : __builtin_inff());
+  };
+  int e = u.e0 + (int)threadIdx.x;
+  for (; e + 7 * 256 < u.e1; e += 8 * 256) {
+    float2 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = gp[e + i * 256];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) take(v[i]);
+  }
+  for (; e < u.e1; e += 256) take(gp[e]);
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    atomicMax(amax + u.p, __float_as_uint(m));
+  }
+}
+
+// FP64 value (|x| < 2^62) rounded to the nearest 64-bit integer.
+__device__ __forceinline__ unsigned long long fixed_round(double x) {
+  const double r = __builtin_rint(x);
+  const double hi = __builtin_floor(r * 0x1p-32);
+  const double lo = __builtin_fma(-hi, 0x1p32, r);  // exact, in [0, 2^32)
+  return ((unsigned long long)(long long)(int)hi << 32) + (unsigned long long)(uint32_t)lo;
+}
+
 __global__ __launch_bounds__(kMomThreads) void k_resample_T(
-    const PlaneInfo* __restrict__ planes, int os, float q, const float2* __restrict__ g,
-    double2* __restrict__ mom) {
-  extern __shared__ double2 part4[];  // [KPB][os*os][4]
-  const int p = blockIdx.y;
-  const PlaneInfo pi = planes[p];
-  const int os2 = os * os;
-  const int kpb = (kMomThreads + os2 - 1) / os2 > 0 ? max(1, kMomThreads / os2) : 1;
-  const int k0 = blockIdx.x * kpb;
+    const ResampleUnit* __restrict__ units, const PlaneInfo* __restrict__ planes, int os,
+    float invOs, float q, int eN, const uint32_t* __restrict__ amax,
+    const float2* __restrict__ g, unsigned long long* __restrict__ fx) {
+  extern __shared__ unsigned long long bins[];  // [8][nrho]: consecutive k in consecutive banks
+  const ResampleUnit un = units[blockIdx.x];
+  const PlaneInfo pi = planes[un.p];
   const int n = pi.nrho;
-  if (k0 >= n) return;
   const int nmax = n - 2;
-  const int S = pi.S, h = pi.h;
+  for (int i = threadIdx.x; i < n * 8; i += kMomThreads) bins[i] = 0ull;
+  const uint32_t am = amax[un.p];
+  if (!(__uint_as_float(am) <= 3.4028235e38f)) return;  // uniform: NaN moments
+  const double sc = __builtin_ldexp(1.0, moment_exponent(am, eN));
+  const double ysc = pi.conj ? -sc : sc;
   const float2* gp = g + pi.out_off;
-  const float qinv = 1.0f / q;
-  for (int pair = threadIdx.x; pair < kpb * os2; pair += blockDim.x) {
-    const int kk = pair / os2;
-    const int f = pair - kk * os2;
-    const int k = k0 + kk;
-    double2 m0 = make_double2(0, 0), m1 = m0, m2 = m0, m3 = m0;
-    if (k < n && k <= nmax) {
-      const int fv = f / os;
-      const int fu = f - fv * os;
-      // candidate radii (in uv cells of the oversampled grid): (k-1)/q .. (k+2)/q
-      const float rlo = fmaxf(0.f, (float)(k - 1) * qinv);
-      const float rhi = (float)(k + 2) * qinv;
-      const int Rhi = (int)ceilf(rhi) + 1;
-      const float rlo2 = rlo * rlo;
-      // rows: Y = os (b - h) - fv with |Y| <= Rhi
-      const int bmin = max(0, (int)floorf((float)(fv - Rhi) / os) + h);
-      const int bmax = min(S - 1, (int)ceilf((float)(fv + Rhi) / os) + h);
-      for (int b = bmin; b <= bmax; ++b) {
-        const int Y = os * (b - h) - fv;
-        const float rem_hi = rhi * rhi - (float)(Y * Y);
-        if (rem_hi < 0.f) continue;
-        const int Xhi = (int)ceilf(sqrtf(rem_hi)) + 1;
-        const float rem_lo = rlo2 - (float)(Y * Y);
-        const int Xlo = rem_lo > 0.f ? max(0, (int)floorf(sqrtf(rem_lo)) - 1) : -1;
-        // runs X in [-Xhi, -Xlo] and [Xlo, Xhi] (one run [-Xhi, Xhi] when Xlo < 0)
-        for (int side = 0; side < 2; ++side) {
-          int xa, xb;
-          if (Xlo < 0) {
-            if (side == 1) break;
-            xa = -Xhi;
-            xb = Xhi;
-          } else if (side == 0) {
-            xa = -Xhi;
-            xb = -Xlo;
-          } else {
-            xa = Xlo == 0 ? 1 : Xlo;
-            xb = Xhi;
+  const int S = pi.S, h = pi.h;
+  __syncthreads();
+  const int lim = pi.lim;
+  auto take = [&](int e, int X, int Y) {
+    const int d2 = X * X + Y * Y;
+    if (d2 > lim) return;
+    int k;
+    float uu;
+    radial_pos(d2, q, nmax, k, uu);
+    const float2 gv = gp[e];
+    const double gx = sc * gv.x, gy = ysc * gv.y;
+    const double u1 = uu, u2 = u1 * u1, u3 = u2 * u1;
+    unsigned long long* bk = bins + k;
+    atomicAdd(bk + 0 * n, fixed_round(gx));
+    atomicAdd(bk + 1 * n, fixed_round(gy));
+    atomicAdd(bk + 2 * n, fixed_round(u1 * gx));
+    atomicAdd(bk + 3 * n, fixed_round(u1 * gy));
+    atomicAdd(bk + 4 * n, fixed_round(u2 * gx));
+    atomicAdd(bk + 5 * n, fixed_round(u2 * gy));
+    atomicAdd(bk + 6 * n, fixed_round(u3 * gx));
+    atomicAdd(bk + 7 * n, fixed_round(u3 * gy));
+  };
+  if (S >= 64) {
+    // Wave w takes the 64-sample chunks w, w + 4, ... of the unit (units
+    // start at multiples of 256); a chunk's first sample is decoded once
+    // and advanced by 256 samples a step, and a chunk crosses at most one
+    // row boundary.
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int e = un.e0 + 64 * wave;
+    int rem;
+    const int R = div_small(e, S, pi.invS, rem);
+    int a0 = rem;
+    const int F = div_small(R, S, pi.invS, rem);
+    int b0 = rem;
+    int fv0 = div_small(F, os, invOs, rem);
+    int fu0 = rem;
+    const int stepA = 256 % S;
+    const int stepR = 256 / S;
+    for (; e < un.e1; e += 256) {
+      if (e + lane < un.e1) {
+        int a = a0 + lane, b = b0, fu = fu0, fv = fv0;
+        if (a >= S) {
+          a -= S;
+          if (++b == S) {
+            b = 0;
+            if (++fu == os) {
+              fu = 0;
+              ++fv;
+            }
           }
-          // a with X = os (a - h) - fu in [xa, xb]
-          int a0 = (xa + fu + os * h + os - 1);
-          a0 = a0 >= 0 ? a0 / os : 0;
-          int a1 = xb + fu + os * h;
-          a1 = a1 >= 0 ? a1 / os : -1;
-          a0 = max(a0, 0);
-          a1 = min(a1, S - 1);
-          for (int a = a0; a <= a1; ++a) {
-            const int X = os * (a - h) - fu;
-            const int d2 = X * X + Y * Y;
-            if (d2 > pi.lim) continue;
-            int kk2;
-            float uu;
-            radial_pos(d2, q, nmax, kk2, uu);
-            if (kk2 != k) continue;
-            float2 gv = gp[((size_t)(f * S + b)) * S + a];
-            if (pi.conj) gv.y = -gv.y;
-            const double u1 = uu, u2 = u1 * u1, u3 = u2 * u1;
-            m0.x += gv.x;
-            m0.y += gv.y;
-            m1.x += u1 * gv.x;
-            m1.y += u1 * gv.y;
-            m2.x += u2 * gv.x;
-            m2.y += u2 * gv.y;
-            m3.x += u3 * gv.x;
-            m3.y += u3 * gv.y;
-          }
+        }
+        take(e + lane, os * (a - h) - fu, os * (b - h) - fv);
+      }
+      a0 += stepA;
+      int c = stepR;
+      if (a0 >= S) {
+        a0 -= S;
+        ++c;
+      }
+      b0 += c;
+      if (b0 >= S) {
+        b0 -= S;
+        if (++fu0 == os) {
+          fu0 = 0;
+          ++fv0;
         }
       }
     }
-    double2* dst = part4 + (size_t)(kk * os2 + f) * 4;
-    dst[0] = m0;
-    dst[1] = m1;
-    dst[2] = m2;
-    dst[3] = m3;
+  } else {
+    for (int e = un.e0 + (int)threadIdx.x; e < un.e1; e += kMomThreads) {
+      int a, b, fu;
+      const int R = div_small(e, S, pi.invS, a);
+      const int F = div_small(R, S, pi.invS, b);
+      const int fv = div_small(F, os, invOs, fu);
+      take(e, os * (a - h) - fu, os * (b - h) - fv);
+    }
   }
   __syncthreads();
-  for (int kk = threadIdx.x; kk < kpb; kk += blockDim.x) {
-    const int k = k0 + kk;
-    if (k >= n) break;
-    double2 acc[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0),
-                      make_double2(0, 0)};
-    for (int f = 0; f < os2; ++f)
-      for (int j = 0; j < 4; ++j) {
-        const double2 v = part4[(size_t)(kk * os2 + f) * 4 + j];
-        acc[j].x += v.x;
-        acc[j].y += v.y;
-      }
-    for (int j = 0; j < 4; ++j) mom[(size_t)(pi.line_off_caller + k) * 4 + j] = acc[j];
+  unsigned long long* dst = fx + (size_t)pi.line_off_caller * 8;
+  for (int i = threadIdx.x; i < n * 8; i += kMomThreads) {
+    const int k = i >> 3;
+    const unsigned long long v = bins[(i & 7) * n + k];
+    if (v) atomicAdd(dst + i, v);
+  }
+}
+
+// Fixed-point bins -> FP64 moments [lineTotalAll][4] (caller order).
+__global__ void k_mom_convert(const PlaneInfo* __restrict__ planes, int eN,
+                              const uint32_t* __restrict__ amax,
+                              const unsigned long long* __restrict__ fx,
+                              double2* __restrict__ mom) {
+  const int p = blockIdx.y;
+  const PlaneInfo pi = planes[p];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= pi.nrho) return;
+  const uint32_t am = amax[p];
+  const bool ok = __uint_as_float(am) <= 3.4028235e38f;
+  const double inv = __builtin_ldexp(1.0, -moment_exponent(am, eN));
+  const size_t L = (size_t)pi.line_off_caller + k;
+  for (int j = 0; j < 4; ++j) {
+    const double re = (double)(long long)fx[L * 8 + 2 * j] * inv;
+    const double im = (double)(long long)fx[L * 8 + 2 * j + 1] * inv;
+    mom[L * 4 + j] = ok ? make_double2(re, im) : make_double2(__builtin_nan(""), __builtin_nan(""));
   }
 }
 
@@ -1617,21 +1699,34 @@ __global__ __launch_bounds__(64) void k_spline_T(int j0, int interp,
 //   G_s[i] = sum_k M[k, i] gy_j[k],  u = G_s exp(-j theta_i),
 //   ure[j][i] = Re u,  wterm[j][i] = 2 pi phi_i tau_i Im u,
 // theta = 2 pi w phi with the phase reduced modulo 1 in FP64.
-__global__ void k_contract_T(int Nr, int NrPad, const int32_t* __restrict__ perm,
-                             const int32_t* __restrict__ nrhoSorted,
-                             const int32_t* __restrict__ lineOffSorted,
-                             const float* __restrict__ M32, const double* __restrict__ phi,
-                             const float* __restrict__ taper, const double* __restrict__ w,
-                             const double2* __restrict__ gy, double* __restrict__ ure,
-                             double* __restrict__ wterm) {
+__global__ __launch_bounds__(256) void k_contract_T(
+    int Nr, int NrPad, const int32_t* __restrict__ perm, const int32_t* __restrict__ nrhoSorted,
+    const int32_t* __restrict__ lineOffSorted, const float* __restrict__ M32,
+    const double* __restrict__ phi, const float* __restrict__ taper,
+    const double* __restrict__ w, const double2* __restrict__ gy, double* __restrict__ ure,
+    double* __restrict__ wterm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= Nr) return;
   const int n = nrhoSorted[j];
   const double2* y = gy + lineOffSorted[j];
+  const float* mcol = M32 + i;
   double gr = 0.0, gi = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double mk = (double)M32[(size_t)k * NrPad + i];
+  int k = 0;
+  // eight loads in flight per step; the sums still run over k in order
+  for (; k + 8 <= n; k += 8) {
+    float mk[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) mk[t] = mcol[(size_t)(k + t) * NrPad];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const double2 v = y[k + t];
+      gr += (double)mk[t] * v.x;
+      gi += (double)mk[t] * v.y;
+    }
+  }
+  for (; k < n; ++k) {
+    const double mk = (double)mcol[(size_t)k * NrPad];
     const double2 v = y[k];
     gr += mk * v.x;
     gi += mk * v.y;
@@ -1646,14 +1741,25 @@ __global__ void k_contract_T(int Nr, int NrPad, const int32_t* __restrict__ perm
   wterm[(size_t)j * NrPad + i] = kTwoPi * phi[i] * (double)taper[i] * ui;
 }
 
-// dL/dtau_i = sum over planes (sorted order) of Re u.
-__global__ void k_grad_taper(int P, int Nr, int NrPad, const double* __restrict__ ure,
-                             float* __restrict__ gtau) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Nr) return;
+// dL/dtau_i = sum over planes (sorted order) of Re u: thread (x, y) of a
+// block adds the planes y, y + 8, ... of node i in order, and the eight
+// partial sums are added in y order (a fixed order: bit-reproducible).
+__global__ __launch_bounds__(256) void k_grad_taper(int P, int Nr, int NrPad,
+                                                    const double* __restrict__ ure,
+                                                    float* __restrict__ gtau) {
+  __shared__ double part[8][32];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int i = blockIdx.x * 32 + tx;
   double acc = 0.0;
-  for (int j = 0; j < P; ++j) acc += ure[(size_t)j * NrPad + i];
-  gtau[i] = (float)acc;
+  if (i < Nr)
+    for (int j = ty; j < P; j += 8) acc += ure[(size_t)j * NrPad + i];
+  part[ty][tx] = acc;
+  __syncthreads();
+  if (ty == 0 && i < Nr) {
+    double t = part[0][tx];
+    for (int g = 1; g < 8; ++g) t += part[g][tx];
+    gtau[i] = (float)t;
+  }
 }
 
 // dL/dw of mirrored planes is folded into their sources.
@@ -1981,19 +2087,32 @@ hipError_t launch_lines_out(const DevPlan& p, void* lines, hipStream_t s) {
 hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* taper,
                        const double* w, const void* gout, float* gtau, double* gw,
                        hipStream_t s) {
-  const int os2 = p.os * p.os;
-  const int kpb = os2 >= kMomThreads ? 1 : kMomThreads / os2;
-  const size_t shm = (size_t)kpb * os2 * 4 * sizeof(double2);
-  if (shm > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_resample_T,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-  }
-  dim3 g1((p.nrhoMax + kpb - 1) / kpb, p.Pall);
-  hipLaunchKernelGGL(k_resample_T, g1, dim3(kMomThreads), shm, s, p.planes, p.os, (float)p.q,
-                     (const float2*)gout, gs.mom);
+  // samples of one interval: at most the lattice points of its ring (radius
+  // (k + 1) / q at most, width 1 / q, widened for the radius rounding)
+  const double rq = (double)p.nrhoMax / p.q;
+  const double ringPts = M_PI * (2.0 * rq / p.q + 2e-6 * rq * rq + 2.0) + 4.0 * M_PI * (rq + 1.0) +
+                         M_PI + 16.0;
+  const int eN = (int)std::ceil(std::log2(ringPts));
+  const int64_t n8 = (int64_t)p.lineTotalAll * 8;
+  hipLaunchKernelGGL(k_grad_clear, dim3(1024), dim3(256), 0, s, n8, gs.momfx, p.Pall, gs.amax);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_absmax, dim3(p.nUnits), dim3(256), 0, s, p.units, p.planes,
+                     (const float2*)gout, gs.amax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t shm = (size_t)p.nrhoMax * 8 * sizeof(unsigned long long);
+  if (shm > 65536) {
+    e = hipFuncSetAttribute((const void*)k_resample_T, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_resample_T, dim3(p.nUnits), dim3(kMomThreads), shm, s, p.units, p.planes,
+                     p.os, 1.0f / (float)p.os, (float)p.q, eN, gs.amax, (const float2*)gout,
+                     gs.momfx);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mom_convert, dim3((p.nrhoMax + 255) / 256, p.Pall), dim3(256), 0, s,
+                     p.planes, eN, gs.amax, gs.momfx, gs.mom);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t shmT = (size_t)3 * p.nrhoMax * sizeof(double2);
   if (shmT > 65536) {
     e = hipFuncSetAttribute((const void*)k_spline_T, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2008,8 +2127,8 @@ hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* tap
   hipLaunchKernelGGL(k_contract_T, g3, dim3(256), 0, s, p.Nr, p.NrPad, p.perm, p.nrhoSorted,
                      p.lineOffSorted, p.M32, p.phi, taper, w, gs.gy, gs.ure, gs.wterm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grad_taper, dim3((p.Nr + 255) / 256), dim3(256), 0, s, p.P, p.Nr,
-                     p.NrPad, gs.ure, gtau);
+  hipLaunchKernelGGL(k_grad_taper, dim3((p.Nr + 31) / 32), dim3(256), 0, s, p.P, p.Nr, p.NrPad,
+                     gs.ure, gtau);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_grad_w, dim3(p.P), dim3(256), 0, s, p.Nr, p.NrPad, p.perm, gs.wterm, gw);
   if ((e = hipGetLastError()) != hipSuccess) return e;
