@@ -188,3 +188,57 @@ def test_grad_with_mirrored_planes():
     assert _rel(gt, gt_ref) <= GATE and _rel(gw, want) <= GATE
     assert np.all(gw[mir >= 0] == 0.0)
     plan.close()
+
+
+def test_grad_fixed_point_edges():
+    """The resample transpose adds its products in 64-bit fixed point with a
+    per-plane power-of-two scale taken from max |G|: scaling G by 2^s scales
+    both gradients by exactly 2^s; G = 0 gives exact zeros; a single nonzero
+    sample matches the oracle; a NaN or an infinity in one plane's G makes
+    that plane's dL/dw and the whole dL/dtaper NaN and leaves the other
+    planes' dL/dw finite."""
+    from paper_1904_08463_amd import Plan
+    wl = W.random_small(51, n_planes=5, n_radial=160, os_=3, max_support=21)
+    plan = Plan.from_workload(wl)
+    taper = torch.from_numpy(wl.taper).cuda()
+    w = torch.from_numpy(wl.w).cuda()
+    rng = np.random.default_rng(5)
+    total = int(plan.offsets[-1])
+    g = (rng.normal(size=total) + 1j * rng.normal(size=total)).astype(np.complex64)
+
+    def run(gn):
+        gt, gw = plan.grad(taper, w, torch.from_numpy(np.ascontiguousarray(gn)).cuda())
+        return gt.cpu().numpy(), gw.cpu().numpy()
+
+    gt, gw = run(g)
+    for s in (-60, 40):
+        gts, gws = run(g * np.float32(2.0 ** s))
+        print(f"scale 2^{s}: taper bit-exact {np.array_equal(gts, gt * np.float32(2.0 ** s))}",
+              flush=True)
+        assert np.array_equal(gts, gt * np.float32(2.0 ** s))
+        assert np.array_equal(gws, gw * 2.0 ** s)
+    gt0, gw0 = run(np.zeros_like(g))
+    assert np.all(gt0 == 0) and np.all(gw0 == 0)
+
+    one = np.zeros_like(g)
+    p1 = 3
+    idx = int(plan.offsets[p1]) + (int(plan.offsets[p1 + 1]) - int(plan.offsets[p1])) // 2 + 1
+    one[idx] = 1.5 - 0.5j
+    gt1, gw1 = run(one)
+    g_caches = [one[plan.offsets[p]:plan.offsets[p + 1]].astype(np.complex128).reshape(
+        wl.oversampling, wl.oversampling, wl.support[p], wl.support[p]) for p in range(wl.n_planes)]
+    gt_ref, gw_ref = A.grad(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling,
+                            wl.taper.astype(np.float64), wl.w, wl.support, g_caches)
+    print(f"single sample: taper err {_rel(gt1, gt_ref):.2e}, w err {_rel(gw1, gw_ref):.2e}",
+          flush=True)
+    assert _rel(gt1, gt_ref) <= GATE and _rel(gw1, gw_ref) <= GATE
+
+    for bad in (np.nan, np.inf):
+        gb = g.copy()
+        p2 = 2
+        gb[int(plan.offsets[p2]) + 7] = np.complex64(complex(bad, 0.0))
+        gtb, gwb = run(gb)
+        others = [p for p in range(wl.n_planes) if p != p2]
+        assert np.isnan(gwb[p2]) and np.all(np.isfinite(gwb[others]))
+        assert np.all(np.isnan(gtb))
+    plan.close()
