@@ -17,7 +17,21 @@ struct PlaneInfo {
   float invS;         // 1 / S (estimate for the exact small division)
   int32_t conj;       // 1: mirrored plane, written as the conjugate of its source
   int32_t line_off_caller;  // offset of its own line in the caller-order layout
+  uint32_t magicS;    // x / S = umulhi(x, magicS) >> shiftS for 0 <= x < 2^24 (S >= 2)
+  int32_t shiftS;
 };
+
+// Multiplier and shift that divide every 0 <= x < 2^24 by d >= 2 exactly:
+// x / d = umulhi(x, m) >> sh.  With L = max(32, 24 + ceil(log2 d)) and
+// m = ceil(2^L / d), x m / 2^L exceeds x / d by less than x / 2^L < 2^-(L-24)
+// <= 1 / d, which cannot carry it past the next integer.
+inline void magic_div24(uint32_t d, uint32_t& m, int32_t& sh) {
+  int l = 0;
+  while ((1u << l) < d) ++l;
+  const int L = l + 24 > 32 ? l + 24 : 32;
+  m = (uint32_t)((((uint64_t)1 << L) + d - 1) / d);
+  sh = L - 32;
+}
 
 // One block of output elements [e0, e1) of plane p (plane-local indices).
 struct ResampleUnit {

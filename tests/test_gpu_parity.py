@@ -288,3 +288,37 @@ def test_longest_radial_line(precision):
     wl.max_support = 255
     wl.radial_refine = 2
     _run_full(wl, precision)
+
+
+@pytest.mark.parametrize("q,os_,smax", [(1, 8, 255), (2, 3, 151), (1, 2, 301)])
+def test_full_cache_bitwise_equals_per_sample_evaluation(q, os_, smax):
+    """The full-cache resample decodes each wave's first sample once and
+    writes two samples per 16-byte store; the truncated path decodes every
+    sample on its own and evaluates it with the shared per-sample routine.
+    Both take the same FP32 steps, so at a threshold far below every node
+    (supports stay full) the two caches agree bit for bit: S >= 128,
+    64 <= S < 128 and S < 64, q = 1 and 2, odd os (8-byte stores where a
+    plane starts at an odd element), mirrored planes."""
+    from paper_1904_08463_amd import Plan
+    base = W.random_small(61, n_planes=2, n_radial=384, os_=os_, max_support=smax,
+                          radial_refine=q)
+    sup = [s for s in (smax, 201, 129, 127, 101, 65, 63, 33, 7, 3, 1) if s <= smax]
+    rng = np.random.default_rng(7)
+    w = rng.uniform(-1200.0, 1200.0, len(sup))
+    # three planes repeated with -w: written as conjugates of their sources
+    w2 = np.concatenate([w, -w[:3]])
+    sup2 = np.array(sup + sup[:3], dtype=np.int32)
+    mir = W.mirror_table(w2, sup2)
+    assert (mir >= 0).sum() == 3
+    plan = Plan(base.image_size, base.cellsize, base.n_radial, os_, sup2, smax,
+                radial_refine=q, precision="bf16x6", mirror=mir)
+    taper = torch.from_numpy(base.taper).cuda()
+    wd = torch.from_numpy(w2).cuda()
+    full = plan.generate(taper, wd)
+    tr, sup_t, offs_t = plan.generate_truncated(taper, wd, frac=1e-30)
+    torch.cuda.synchronize()
+    print(f"q={q} os={os_}: supports {sup2.tolist()}", flush=True)
+    assert np.array_equal(sup_t.cpu().numpy(), sup2)
+    assert np.array_equal(offs_t.cpu().numpy(), plan.offsets)
+    assert torch.equal(full.view(torch.int32), tr.view(torch.int32))
+    plan.close()
