@@ -87,18 +87,27 @@ __device__ __forceinline__ float2 screen_value(double wv, double ph, float tau) 
   return make_float2(tau * c2, tau * s2);
 }
 
-// FP32 screen: B32[2j + c][i], sorted plane j, c = 0 (re) / 1 (im).
-__global__ void k_screen_f32(int j0, int j1, int Nr, int NrPad, const int32_t* __restrict__ perm,
-                             const double* __restrict__ phi, const float* __restrict__ taper,
-                             const double* __restrict__ w, float* __restrict__ B32) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= NrPad) return;
+// FP32 screen: B32[2j + c][i], sorted plane j, c = 0 (re) / 1 (im).  A
+// thread computes four consecutive nodes and writes each row's four values
+// with one 16-byte store (NrPad is a multiple of 256).
+__global__ __launch_bounds__(256) void k_screen_f32(int j0, int j1, int Nr, int NrPad,
+                                                    const int32_t* __restrict__ perm,
+                                                    const double* __restrict__ phi,
+                                                    const float* __restrict__ taper,
+                                                    const double* __restrict__ w,
+                                                    float* __restrict__ B32) {
+  const int i0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (i0 >= NrPad) return;
   for (int j = j0 + blockIdx.y; j < j1; j += gridDim.y) {
     const double wv = w[perm[j]];
-    float2 v = make_float2(0.f, 0.f);
-    if (i < Nr) v = screen_value(wv, phi[i], taper[i]);
-    B32[(size_t)(2 * j) * NrPad + i] = v.x;
-    B32[(size_t)(2 * j + 1) * NrPad + i] = v.y;
+    float4 re = make_float4(0.f, 0.f, 0.f, 0.f), im = re;
+    float2 v;
+    if (i0 < Nr) { v = screen_value(wv, phi[i0], taper[i0]); re.x = v.x; im.x = v.y; }
+    if (i0 + 1 < Nr) { v = screen_value(wv, phi[i0 + 1], taper[i0 + 1]); re.y = v.x; im.y = v.y; }
+    if (i0 + 2 < Nr) { v = screen_value(wv, phi[i0 + 2], taper[i0 + 2]); re.z = v.x; im.z = v.y; }
+    if (i0 + 3 < Nr) { v = screen_value(wv, phi[i0 + 3], taper[i0 + 3]); re.w = v.x; im.w = v.y; }
+    *(float4*)(B32 + (size_t)(2 * j) * NrPad + i0) = re;
+    *(float4*)(B32 + (size_t)(2 * j + 1) * NrPad + i0) = im;
   }
 }
 
@@ -1903,7 +1912,7 @@ hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, c
   if (j1 <= j0) return hipSuccess;
   const int gy = (j1 - j0) < 65535 ? (j1 - j0) : 65535;
   if (fp32) {
-    dim3 grid((p.NrPad + 255) / 256, gy);
+    dim3 grid((p.NrPad / 4 + 255) / 256, gy);
     hipLaunchKernelGGL(k_screen_f32, grid, dim3(256), 0, s, j0, j1, p.Nr, p.NrPad, p.perm, p.phi,
                        taper, w, p.B32);
   } else {
