@@ -10,11 +10,11 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------------------
-// Oversampled kernel cache (section 4.4, Algorithm 2).  Each block writes
-// the elements [e0, e1) of one plane, e = ((fv os + fu) S + b) S + a; the
-// plane's spline intervals are staged in LDS.  Stores are coalesced
-// (consecutive lanes, consecutive elements) and non-temporal: the cache is
-// written once and read by a later consumer.
+// Oversampled kernel cache (section 4.4, Algorithm 2), element
+// e = ((fv os + fu) S + b) S + a of a plane.  resample_range below writes a
+// range of elements sample by sample (the truncated layout uses it); the
+// full cache uses k_resample further down, which takes the same FP32 steps
+// per sample with a cheaper position decode.
 //
 // Radius in units of the radial node spacing: t = q sqrt(d2), d2 = X^2 + Y^2
 // (an integer, exact in FP32).  Rounding t itself to FP32 would cost up to
@@ -26,7 +26,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // u slightly outside [0, 1), where the neighbouring cubic piece agrees.
 // --------------------------------------------------------------------------
 
-// Writes elements [e0, e1) of one plane (its spline intervals already in sc).
+// Writes elements [e0, e1) of one plane (its spline intervals already in sc)
+// with coalesced non-temporal 8-byte stores.
 __device__ __forceinline__ void resample_range(const PlaneInfo& pi, int e0, int e1, int os,
                                                float invOs, float q,
                                                const float4* __restrict__ sc,
