@@ -290,15 +290,16 @@ def test_longest_radial_line(precision):
     _run_full(wl, precision)
 
 
-@pytest.mark.parametrize("q,os_,smax", [(1, 8, 255), (2, 3, 151), (1, 2, 301)])
+@pytest.mark.parametrize("q,os_,smax", [(1, 8, 255), (2, 3, 151), (1, 2, 301), (1, 1, 301), (1, 5, 201)])
 def test_full_cache_bitwise_equals_per_sample_evaluation(q, os_, smax):
     """The full-cache resample decodes each wave's first sample once and
     writes two samples per 16-byte store; the truncated path decodes every
     sample on its own and evaluates it with the shared per-sample routine.
     Both take the same FP32 steps, so at a threshold far below every node
     (supports stay full) the two caches agree bit for bit: S >= 128,
-    64 <= S < 128 and S < 64, q = 1 and 2, odd os (8-byte stores where a
-    plane starts at an odd element), mirrored planes."""
+    64 <= S < 128 and S < 64, q = 1 and 2, os = 1 (no sub-kernel split),
+    odd os (8-byte stores where a plane starts at an odd element; os = 5 by
+    magic-number division), mirrored planes."""
     from paper_1904_08463_amd import Plan
     base = W.random_small(61, n_planes=2, n_radial=384, os_=os_, max_support=smax,
                           radial_refine=q)
