@@ -209,7 +209,11 @@ wkern_status wkern_prepare_lines(wkern_plan_t plan, const float* taper, const do
  * vis:          device complex64 [n_records].
  * order, plane_start: the partition (wkern_wpartition) over the plan's P
  *               planes: plane m grids records order[plane_start[m] ..
- *               plane_start[m + 1] - 1].
+ *               plane_start[m + 1] - 1].  plane_start (device int64
+ *               [P + 1]) starts at 0 and does not decrease; order (device
+ *               int32 [plane_start[P]]) holds indices in [0, n_records), a
+ *               subset of the records or all of them.  Both are read on the
+ *               device as given.
  * support:      device int32 [P], odd widths; each at most the planned one.
  * cache:        NULL: fused, the kernel values come from the spline
  *               coefficients of the plan's last wkern_prepare_lines or

@@ -850,11 +850,14 @@ static wkern_status ensure_trunc_scratch(wkern_plan_t plan) {
   const DevPlan& g = plan->dp;
   TruncScratch& ts = plan->trunc;
   wkern_status s;
-  if ((s = plan->alloc(&ts.hTrunc, (size_t)g.P, "truncation table")) != WKERN_OK) return s;
-  if ((s = plan->alloc(&ts.unitStart, (size_t)g.Pall + 1, "truncation table")) != WKERN_OK)
+  if ((s = plan->alloc(&ts.hTrunc, (size_t)g.P, "truncation table")) != WKERN_OK ||
+      (s = plan->alloc(&ts.unitStart, (size_t)g.Pall + 1, "truncation table")) != WKERN_OK ||
+      (s = plan->upload(&ts.sortedPos, plan->sortedPosOfCaller, "truncation table")) != WKERN_OK) {
+    plan->release(ts.hTrunc);
+    plan->release(ts.unitStart);
+    plan->release(ts.sortedPos);
     return s;
-  if ((s = plan->upload(&ts.sortedPos, plan->sortedPosOfCaller, "truncation table")) != WKERN_OK)
-    return s;
+  }
   plan->truncReady = true;
   return WKERN_OK;
 }
@@ -1070,15 +1073,22 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
   if (!plan->gradReady) {
     GradScratch& gs = plan->grad;
     const size_t lt = (size_t)g.lineTotal;
-    if ((s = plan->alloc(&gs.mom, (size_t)g.lineTotalAll * 4, "adjoint moments")) != WKERN_OK)
-      return s;
-    if ((s = plan->alloc(&gs.gy, lt, "adjoint lines")) != WKERN_OK) return s;
     const size_t pn = (size_t)g.P * g.NrPad;
-    if ((s = plan->alloc(&gs.ure, pn, "adjoint screen")) != WKERN_OK) return s;
-    if ((s = plan->alloc(&gs.wterm, pn, "adjoint screen")) != WKERN_OK) return s;
-    if ((s = plan->alloc(&gs.momfx, (size_t)g.lineTotalAll * 8, "adjoint moments")) != WKERN_OK)
+    if ((s = plan->alloc(&gs.mom, (size_t)g.lineTotalAll * 4, "adjoint moments")) != WKERN_OK ||
+        (s = plan->alloc(&gs.gy, lt, "adjoint lines")) != WKERN_OK ||
+        (s = plan->alloc(&gs.ure, pn, "adjoint screen")) != WKERN_OK ||
+        (s = plan->alloc(&gs.wterm, pn, "adjoint screen")) != WKERN_OK ||
+        (s = plan->alloc(&gs.momfx, (size_t)g.lineTotalAll * 8, "adjoint moments")) != WKERN_OK ||
+        (s = plan->alloc(&gs.amax, (size_t)g.Pall, "adjoint maxima")) != WKERN_OK) {
+      // release what was allocated, so that a later call starts clean
+      plan->release(gs.mom);
+      plan->release(gs.gy);
+      plan->release(gs.ure);
+      plan->release(gs.wterm);
+      plan->release(gs.momfx);
+      plan->release(gs.amax);
       return s;
-    if ((s = plan->alloc(&gs.amax, (size_t)g.Pall, "adjoint maxima")) != WKERN_OK) return s;
+    }
     plan->gradReady = true;
   }
   WK_HIP(launch_grad(g, plan->grad, taper, w, grad_out, grad_taper, grad_w, (hipStream_t)stream),

@@ -193,6 +193,20 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _require(t, dtype, name, numel=None, device=None):
+    """Raise ValueError unless t is a contiguous device tensor of dtype (with
+    numel values, on the given device index): the library reads and writes
+    these pointers on the device without knowing their extent."""
+    import torch
+    ok = (isinstance(t, torch.Tensor) and t.dtype == dtype and t.is_cuda and t.is_contiguous()
+          and (numel is None or t.numel() == numel)
+          and (device is None or t.device.index == device))
+    if not ok:
+        size = f" of {numel} values" if numel is not None else ""
+        where = f" on cuda:{device}" if device is not None else ""
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor{size}{where}")
+
+
 class Plan:
     """A wkern plan (geometry, HT matrix, schedule, scratch) on one device."""
 
@@ -229,12 +243,8 @@ class Plan:
     # ------------------------------------------------------------------
     def _check_inputs(self, taper, w):
         import torch
-        if taper.dtype != torch.float32 or not taper.is_cuda or taper.numel() != self.n_radial:
-            raise ValueError(f"taper must be a CUDA float32 tensor of {self.n_radial} values")
-        if w.dtype != torch.float64 or not w.is_cuda or w.numel() != self.n_planes:
-            raise ValueError(f"w must be a CUDA float64 tensor of {self.n_planes} values")
-        if not taper.is_contiguous() or not w.is_contiguous():
-            raise ValueError("taper and w must be contiguous")
+        _require(taper, torch.float32, "taper", numel=self.n_radial, device=self.device)
+        _require(w, torch.float64, "w", numel=self.n_planes, device=self.device)
 
     def generate(self, taper, w, out=None, stream=None):
         """Kernel cache as a flat complex64 tensor [offsets[P]] (asynchronous)."""
@@ -243,8 +253,7 @@ class Plan:
         total = int(self.offsets[-1])
         if out is None:
             out = torch.empty(total, dtype=torch.complex64, device=taper.device)
-        elif out.dtype != torch.complex64 or out.numel() != total or not out.is_contiguous():
-            raise ValueError(f"out must be a contiguous complex64 tensor of {total} values")
+        _require(out, torch.complex64, "out", numel=total, device=self.device)
         _check(load_library().wkern_generate(self._h, _ptr(taper), _ptr(w), _ptr(out),
                                              _stream_handle(stream)))
         return out
@@ -257,6 +266,8 @@ class Plan:
         total = int(self.offsets[-1])
         if out is None:
             out = torch.empty(total, dtype=torch.complex64, device=taper.device)
+        # the library checks the capacity it is given against the cache size
+        _require(out, torch.complex64, "out", device=self.device)
         sup = torch.empty(self.n_planes, dtype=torch.int32, device=taper.device)
         offs = torch.empty(self.n_planes + 1, dtype=torch.int64, device=taper.device)
         _check(load_library().wkern_generate_truncated(
@@ -271,6 +282,7 @@ class Plan:
         total = int(self.nrho.sum())
         if out is None:
             out = torch.empty(total, dtype=torch.complex128, device=taper.device)
+        _require(out, torch.complex128, "out", numel=total, device=self.device)
         _check(load_library().wkern_generate_radial(self._h, _ptr(taper), _ptr(w), _ptr(out),
                                                     _stream_handle(stream)))
         return out
@@ -280,13 +292,14 @@ class Plan:
         import torch
         self._check_inputs(taper, w)
         total = int(self.offsets[-1])
-        if grad_out.dtype != torch.complex64 or grad_out.numel() != total:
-            raise ValueError("grad_out must be complex64 with the cache's size")
         grad_out = grad_out.contiguous()
+        _require(grad_out, torch.complex64, "grad_out", numel=total, device=self.device)
         if grad_taper is None:
             grad_taper = torch.empty(self.n_radial, dtype=torch.float32, device=taper.device)
         if grad_w is None:
             grad_w = torch.empty(self.n_planes, dtype=torch.float64, device=taper.device)
+        _require(grad_taper, torch.float32, "grad_taper", numel=self.n_radial, device=self.device)
+        _require(grad_w, torch.float64, "grad_w", numel=self.n_planes, device=self.device)
         _check(load_library().wkern_grad(self._h, _ptr(taper), _ptr(w), _ptr(grad_out),
                                          _ptr(grad_taper), _ptr(grad_w), _stream_handle(stream)))
         return grad_taper, grad_w
@@ -330,6 +343,7 @@ class Plan:
         self._check_inputs(taper, w)
         if support_out is None:
             support_out = torch.empty(self.n_planes, dtype=torch.int32, device=taper.device)
+        _require(support_out, torch.int32, "support_out", numel=self.n_planes, device=self.device)
         _check(load_library().wkern_prepare_lines(self._h, _ptr(taper), _ptr(w), ctypes.c_double(frac),
                                                   _ptr(support_out), _stream_handle(stream)))
         return support_out
@@ -339,16 +353,22 @@ class Plan:
         """Add every record's kernel footprint onto grid (complex64 [N, N]):
         fused from the prepared lines (cache None) or from a kernel cache."""
         import torch
-        for t, dt in ((u, torch.float64), (v, torch.float64), (w, torch.float64),
-                      (vis, torch.complex64), (order, torch.int32), (plane_start, torch.int64),
-                      (support, torch.int32), (grid, torch.complex64)):
-            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
-                raise ValueError("gridding arguments must be contiguous device tensors of "
-                                 "the documented dtypes")
+        n = u.numel() if isinstance(u, torch.Tensor) else -1
+        P, dev = self.n_planes, self.device
+        for t, dt, name, cnt in ((u, torch.float64, "u", n), (v, torch.float64, "v", n),
+                                 (w, torch.float64, "w", n), (vis, torch.complex64, "vis", n),
+                                 (order, torch.int32, "order", None),
+                                 (plane_start, torch.int64, "plane_start", P + 1),
+                                 (support, torch.int32, "support", P)):
+            _require(t, dt, name, numel=cnt, device=dev)
+        _require(grid, torch.complex64, "grid", device=dev)
         if grid.dim() != 2 or grid.shape[0] != grid.shape[1]:
             raise ValueError("grid must be square")
-        if cache is not None and (cache.dtype != torch.complex64 or cache_offsets is None):
-            raise ValueError("cache must be complex64 with device cache_offsets")
+        if (cache is None) != (cache_offsets is None):
+            raise ValueError("cache and cache_offsets go together")
+        if cache is not None:
+            _require(cache, torch.complex64, "cache", device=dev)
+            _require(cache_offsets, torch.int64, "cache_offsets", numel=P + 1, device=dev)
         _check(load_library().wkern_grid(
             self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(vis), u.numel(), _ptr(order),
             _ptr(plane_start), _ptr(support), None if cache is None else _ptr(cache),
@@ -410,6 +430,7 @@ class FFT2DPlan:
         _check(lib.wkern_fft2d_plan(ctypes.byref(d), self.WORKSPACE[workspace],
                                     int(workspace_bytes), ctypes.byref(h)))
         self._h = h
+        self.device = int(device)
         self.n_planes = int(d.n_planes)
         self.n_radial = int(n_radial)
         self.offsets, _ = layout_desc(image_size=image_size, cellsize=cellsize, n_radial=n_radial,
@@ -425,8 +446,11 @@ class FFT2DPlan:
     def generate(self, taper, w, out=None, stream=None):
         import torch
         total = int(self.offsets[-1])
+        _require(taper, torch.float32, "taper", numel=self.n_radial, device=self.device)
+        _require(w, torch.float64, "w", numel=self.n_planes, device=self.device)
         if out is None:
             out = torch.empty(total, dtype=torch.complex64, device=taper.device)
+        _require(out, torch.complex64, "out", numel=total, device=self.device)
         _check(load_library().wkern_fft2d_generate(self._h, _ptr(taper), _ptr(w), _ptr(out),
                                                    _stream_handle(stream)))
         return out
@@ -470,6 +494,7 @@ def wpartition(w, n_planes: int, absolute: bool = True, stat: str = "mean", work
     if workspace is None:
         workspace = torch.empty(wpartition_workspace(n, dev.index or 0), dtype=torch.uint8,
                                 device=dev)
+    _require(workspace, torch.uint8, "workspace", device=dev.index)
     order = torch.empty(n, dtype=torch.int32, device=dev)
     start = torch.empty(n_planes + 1, dtype=torch.int64, device=dev)
     w_plane = torch.empty(n_planes, dtype=torch.float64, device=dev)

@@ -143,3 +143,18 @@ def test_mirror_table_of_batch_workload():
     assert np.all(m[src] == -1)
     assert np.all(wl.w[m >= 0] == -wl.w[src])
     assert np.all(wl.support[m >= 0] == wl.support[src])
+
+
+def test_binding_rejects_host_and_mis_sized_tensors():
+    """The binding refuses, before any library call, a tensor the library
+    would address on the device: host memory, wrong dtype, wrong size,
+    non-contiguous."""
+    torch = pytest.importorskip("torch")
+    req = lib_mod._require
+    with pytest.raises(ValueError):
+        req(torch.zeros(4, dtype=torch.float32), torch.float32, "t", numel=4)
+    with pytest.raises(ValueError):
+        req(np.zeros(4, dtype=np.float32), torch.float32, "t")
+    meta = torch.empty(8, dtype=torch.float64, device="meta")
+    with pytest.raises(ValueError):
+        req(meta, torch.float64, "t")
