@@ -1241,6 +1241,9 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
                                                float4* __restrict__ coef, double frac2,
                                                int qos, int32_t* __restrict__ hTrunc) {
   extern __shared__ double2 smem[];
+  // c'_k for k < 64; the recurrence reaches its FP64 fixed point by k = 15,
+  // so c'_k = c'_63 for every k >= 63
+  __shared__ double cpL[64];
   const int j = j0 + blockIdx.x;
   const int lane = threadIdx.x;
   const int n = nrhoSorted[j];
@@ -1248,15 +1251,29 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
   double2* y = smem;           // [n] radial line
   double2* dp = smem + n;      // [n] eliminated right-hand side d'
   double2* m = smem + 2 * n;   // [n] second derivatives
+  cpL[lane] = cprime[min(lane, n - 1)];
+  auto cp = [&](int k) { return cpL[min(k, 63)]; };
 
-  for (int k = lane; k < n; k += 64) {
-    double re = 0.0, im = 0.0;
+  // the K-chunk partial sums, added in chunk order, eight nodes per lane in
+  // flight (loads past the line re-read its last node and are dropped)
+  const double2* partL = (const double2*)part + off;
+  for (int k0 = lane; k0 < n; k0 += 64 * 8) {
+    double2 acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = make_double2(0.0, 0.0);
     for (int c = 0; c < nkc; ++c) {
-      const double2 v = ((const double2*)part)[(size_t)c * lineTotal + off + k];
-      re += v.x;
-      im += v.y;
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partL[(size_t)c * lineTotal + min(k0 + 64 * u, n - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        acc[u].x += v[u].x;
+        acc[u].y += v[u].y;
+      }
     }
-    y[k] = make_double2(re, im);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + 64 * u < n) y[k0 + 64 * u] = acc[u];
   }
   __syncthreads();
 
@@ -1282,18 +1299,19 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
     {
       const int start = max(0, s - kSplineWarm);
       double2 prev = make_double2(0.0, 0.0);
+#pragma unroll 4
       for (int k = start; k < e; ++k) {
         double2 v;
         if (k == n - 1) {
           v = make_double2(0.0, 0.0);
         } else if (k == 0) {
-          v.x = 6.0 * (y[1].x - y[0].x) * cprime[0];
-          v.y = 6.0 * (y[1].y - y[0].y) * cprime[0];
+          v.x = 6.0 * (y[1].x - y[0].x) * cp(0);
+          v.y = 6.0 * (y[1].y - y[0].y) * cp(0);
         } else {
           const double dx = 6.0 * (y[k - 1].x - 2.0 * y[k].x + y[k + 1].x);
           const double dy = 6.0 * (y[k - 1].y - 2.0 * y[k].y + y[k + 1].y);
-          v.x = (dx - prev.x) * cprime[k];
-          v.y = (dy - prev.y) * cprime[k];
+          v.x = (dx - prev.x) * cp(k);
+          v.y = (dy - prev.y) * cp(k);
         }
         prev = v;
         if (k >= s) dp[k] = v;
@@ -1304,13 +1322,14 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
     {
       const int top = min(n - 1, e - 1 + kSplineWarm);
       double2 next = make_double2(0.0, 0.0);  // m_{top + 1}; exact when top == n-1
+#pragma unroll 4
       for (int k = top; k >= s; --k) {
         double2 v;
         if (k == n - 1) {
           v = make_double2(0.0, 0.0);
         } else {
-          v.x = dp[k].x - cprime[k] * next.x;
-          v.y = dp[k].y - cprime[k] * next.y;
+          v.x = dp[k].x - cp(k) * next.x;
+          v.y = dp[k].y - cp(k) * next.y;
         }
         next = v;
         if (k < e) m[k] = v;
@@ -1324,11 +1343,15 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
     if (k <= n - 2) {
       const double2 y0 = y[k], y1 = y[k + 1];
       if (interp == 1) {
+        // thirds and sixths as products with the rounded reciprocals (within
+        // an FP64 ulp of the quotients, far below the FP32 the coefficients
+        // are stored in; an FP64 division costs about ten instructions)
         const double2 m0 = m[k], m1 = m[k + 1];
-        cr = make_float4((float)y0.x, (float)(y1.x - y0.x - m0.x / 3.0 - m1.x / 6.0),
-                         (float)(0.5 * m0.x), (float)((m1.x - m0.x) / 6.0));
-        ci = make_float4((float)y0.y, (float)(y1.y - y0.y - m0.y / 3.0 - m1.y / 6.0),
-                         (float)(0.5 * m0.y), (float)((m1.y - m0.y) / 6.0));
+        const double r3 = 1.0 / 3.0, r6 = 1.0 / 6.0;
+        cr = make_float4((float)y0.x, (float)(y1.x - y0.x - m0.x * r3 - m1.x * r6),
+                         (float)(0.5 * m0.x), (float)((m1.x - m0.x) * r6));
+        ci = make_float4((float)y0.y, (float)(y1.y - y0.y - m0.y * r3 - m1.y * r6),
+                         (float)(0.5 * m0.y), (float)((m1.y - m0.y) * r6));
       } else {
         cr = make_float4((float)y0.x, (float)(y1.x - y0.x), 0.f, 0.f);
         ci = make_float4((float)y0.y, (float)(y1.y - y0.y), 0.f, 0.f);
