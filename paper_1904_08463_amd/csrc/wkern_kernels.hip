@@ -89,7 +89,10 @@ __device__ __forceinline__ float2 screen_value(double wv, double ph, float tau) 
 
 // FP32 screen: B32[2j + c][i], sorted plane j, c = 0 (re) / 1 (im).  A
 // thread computes four consecutive nodes and writes each row's four values
-// with one 16-byte store (NrPad is a multiple of 256).
+// with one 16-byte store (NrPad is a multiple of 256).  A workgroup walks
+// planes j0 + blockIdx.y, + gridDim.y, ...: the nodes' phi and taper are
+// loaded once, and the next plane's w is loaded while the current one is
+// computed.
 __global__ __launch_bounds__(256) void k_screen_f32(int j0, int j1, int Nr, int NrPad,
                                                     const int32_t* __restrict__ perm,
                                                     const double* __restrict__ phi,
@@ -97,17 +100,29 @@ __global__ __launch_bounds__(256) void k_screen_f32(int j0, int j1, int Nr, int 
                                                     const double* __restrict__ w,
                                                     float* __restrict__ B32) {
   const int i0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
-  if (i0 >= NrPad) return;
-  for (int j = j0 + blockIdx.y; j < j1; j += gridDim.y) {
-    const double wv = w[perm[j]];
+  int j = j0 + (int)blockIdx.y;
+  if (i0 >= NrPad || j >= j1) return;
+  double ph[4];
+  float ta[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    ph[u] = i0 + u < Nr ? phi[i0 + u] : 0.0;
+    ta[u] = i0 + u < Nr ? taper[i0 + u] : 0.f;
+  }
+  double wv = w[perm[j]];
+  while (j < j1) {
+    const int jn = j + (int)gridDim.y;
+    const double wn = jn < j1 ? w[perm[jn]] : 0.0;
     float4 re = make_float4(0.f, 0.f, 0.f, 0.f), im = re;
     float2 v;
-    if (i0 < Nr) { v = screen_value(wv, phi[i0], taper[i0]); re.x = v.x; im.x = v.y; }
-    if (i0 + 1 < Nr) { v = screen_value(wv, phi[i0 + 1], taper[i0 + 1]); re.y = v.x; im.y = v.y; }
-    if (i0 + 2 < Nr) { v = screen_value(wv, phi[i0 + 2], taper[i0 + 2]); re.z = v.x; im.z = v.y; }
-    if (i0 + 3 < Nr) { v = screen_value(wv, phi[i0 + 3], taper[i0 + 3]); re.w = v.x; im.w = v.y; }
+    if (i0 < Nr) { v = screen_value(wv, ph[0], ta[0]); re.x = v.x; im.x = v.y; }
+    if (i0 + 1 < Nr) { v = screen_value(wv, ph[1], ta[1]); re.y = v.x; im.y = v.y; }
+    if (i0 + 2 < Nr) { v = screen_value(wv, ph[2], ta[2]); re.z = v.x; im.z = v.y; }
+    if (i0 + 3 < Nr) { v = screen_value(wv, ph[3], ta[3]); re.w = v.x; im.w = v.y; }
     *(float4*)(B32 + (size_t)(2 * j) * NrPad + i0) = re;
     *(float4*)(B32 + (size_t)(2 * j + 1) * NrPad + i0) = im;
+    j = jn;
+    wv = wn;
   }
 }
 
@@ -1930,15 +1945,20 @@ hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s) {
   return hipGetLastError();
 }
 
+constexpr int kScreenPlanes = 8;
+
 hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, const double* w,
                          bool fp32, hipStream_t s) {
   if (j1 <= j0) return hipSuccess;
-  const int gy = (j1 - j0) < 65535 ? (j1 - j0) : 65535;
   if (fp32) {
+    // about kScreenPlanes planes per workgroup
+    const int want = (j1 - j0 + kScreenPlanes - 1) / kScreenPlanes;
+    const int gy = want < 65535 ? want : 65535;
     dim3 grid((p.NrPad / 4 + 255) / 256, gy);
     hipLaunchKernelGGL(k_screen_f32, grid, dim3(256), 0, s, j0, j1, p.Nr, p.NrPad, p.perm, p.phi,
                        taper, w, p.B32);
   } else {
+    const int gy = (j1 - j0) < 65535 ? (j1 - j0) : 65535;
     dim3 grid((p.NrPad / 8 + 255) / 256, gy);
     hipLaunchKernelGGL(k_screen_bf16, grid, dim3(256), 0, s, j0, j1, p.Nr, p.NrPad, p.perm,
                        p.phi, taper, w, p.Bsplit);
