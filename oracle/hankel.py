@@ -9,8 +9,7 @@ Scaife (2019), section 4 and Algorithm 2, in the paper's order:
   -> spline through the radial line with precomputed coefficients (4.3.2)
   -> oversampled 2D kernels over the circular support (4.4, Algorithm 2).
 
-Readings taken where the paper is silent or ambiguous (each is also listed
-in the design notes):
+Readings taken where the paper is silent or ambiguous:
 
 R1  Screen sign: G = exp(-j 2 pi w (n - 1)) with n = sqrt(1 - r^2), i.e.
     s(r) = tau(r) exp(+j 2 pi w phi(r)) with phi = 1 - n, evaluated in the
