@@ -62,7 +62,7 @@ typedef enum {
   WKERN_ERR_INVALID_ARG = 1,   /* argument fails validation; nothing enqueued */
   WKERN_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
   WKERN_ERR_DEVICE = 3,        /* no usable device or a HIP runtime error */
-  WKERN_ERR_UNSUPPORTED = 4,   /* valid request this build does not implement */
+  WKERN_ERR_UNSUPPORTED = 4,   /* valid request outside what the library implements */
   WKERN_ERR_ABI_MISMATCH = 5   /* desc->abi_version != WKERN_ABI_VERSION */
 } wkern_status;
 
