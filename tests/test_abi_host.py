@@ -59,6 +59,9 @@ BAD = [
     ("image_size", 0), ("cellsize", 0.0), ("cellsize", float("nan")), ("cellsize", 0.02),
     ("n_radial", 0), ("oversampling", 0), ("oversampling", 65), ("radial_refine", 0),
     ("max_support", 4), ("precision", 7), ("interp", 3),
+    # an empty batch, and sizes past the documented limits
+    ("n_planes", 0), ("n_radial", (1 << 20) + 1), ("radial_refine", 17), ("image_size", -5),
+    ("max_support", 0),
 ]
 
 
