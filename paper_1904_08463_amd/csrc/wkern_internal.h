@@ -57,8 +57,7 @@ enum ContractVariant {
   // multiplied on the FP32 matrix cores (FP32)
   kRingF128x128 = 7,
   kRingF64x256 = 8,
-  // split-BF16 only: the 64 x 256 FP32-operand ring on 8 waves of 32 x 64
-  // (two waves per SIMD)
+  // the 64 x 256 FP32-operand ring on 8 waves of 32 x 64 (two waves per SIMD)
   kRingF64x256W8 = 9,
   kNumVariants = 10
 };
@@ -72,7 +71,6 @@ struct ContractShape {
 ContractShape contract_shape(int variant);
 // The BF16-term ring variants exist for the split-BF16 contraction only.
 inline bool variant_supported(int precision, int variant) {
-  if (variant == kRingF64x256W8) return precision == 1;
   return variant < kRing128x128 || variant >= kRingF128x128 || precision == 1;
 }
 // Whether a variant reads the FP32 screen (B32) rather than its BF16 terms.

@@ -1076,17 +1076,22 @@ __global__ __launch_bounds__(64 * WR * WC) void k_contract_bf16x6_ringf(
 // sums over kSubChunk nodes added to FP64 running sums.
 // --------------------------------------------------------------------------
 template <int WR, int WC, int RBW, int CBW, int NS>
-__global__ __launch_bounds__(256) void k_contract_f32_ringf(
+__global__ __launch_bounds__(64 * WR * WC) void k_contract_f32_ringf(
     const Tile* __restrict__ tiles, int NrPad, int kchunk, int P, int lineTotal,
     const float* __restrict__ M32, const float* __restrict__ B32,
     const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
     double* __restrict__ part) {
   constexpr int BM = 32 * RBW * WR;
   constexpr int BN = 32 * CBW * WC;
+  constexpr int NT = 64 * WR * WC;          // threads
   constexpr int AU = BM * 4;                // 16-byte quarters of M per stage
   constexpr int SU = AU + BN * 4;           // quarters per stage
-  constexpr int LW = (SU + 255) / 256;      // load instructions per wave per stage
-  constexpr int SLOT = LW * 256;
+  // LF load rounds of every wave, then one more by the first RW waves
+  constexpr int LF = SU / NT;
+  constexpr int RW = (SU - LF * NT) / 64;
+  constexpr int LW = LF + (RW > 0 ? 1 : 0);
+  constexpr int SLOT = SU;
+  static_assert(SU % 64 == 0, "whole waves of quarters");
   static_assert(LW * (NS - 2) < 64, "too many loads in flight for vmcnt");
   static_assert(NS == 4 || NS == 8, "ring depth");
   __shared__ float4 ring0[SLOT];
@@ -1113,8 +1118,8 @@ __global__ __launch_bounds__(256) void k_contract_f32_ringf(
   const float* src[LW];
 #pragma unroll
   for (int l = 0; l < LW; ++l) {
-    int u = 256 * l + tid;
-    if (u >= SU) u = 0;
+    int u = NT * l + tid;
+    if (u >= SU) u = 0;  // waves past the last partial round: never issued
     if (u < AU) {
       const int r = u >> 2;
       const int qd = (u & 3) ^ ((r >> 2) & 3);
@@ -1153,10 +1158,11 @@ __global__ __launch_bounds__(256) void k_contract_f32_ringf(
     float4* slot = slot_of(kc);
 #pragma unroll
     for (int l = 0; l < LW; ++l)
-      __builtin_amdgcn_global_load_lds((const void*)(src[l] + (size_t)stage * 16),
-                                       (__attribute__((address_space(3))) void*)(slot + 256 * l +
-                                                                                 64 * wave),
-                                       16, 0, 0);
+      if (l < LF || wave < RW)  // wave-uniform
+        __builtin_amdgcn_global_load_lds((const void*)(src[l] + (size_t)stage * 16),
+                                         (__attribute__((address_space(3))) void*)(slot + NT * l +
+                                                                                   64 * wave),
+                                         16, 0, 0);
   };
   auto barrier = [&]() {
     asm volatile("" ::: "memory");
@@ -1172,10 +1178,14 @@ __global__ __launch_bounds__(256) void k_contract_f32_ringf(
   auto step = [&](auto kc, int s) {
     constexpr int K = decltype(kc)::value;
     constexpr int KN = (K + NS - 1) % NS;
-    if (s + NS - 2 < nst)
-      wait_vmcnt<LW * (NS - 2)>();
-    else
+    if (s + NS - 2 < nst) {
+      if (RW == 0 || wave < RW)
+        wait_vmcnt<LW * (NS - 2)>();
+      else
+        wait_vmcnt<LF * (NS - 2)>();
+    } else {
       wait_vmcnt<0>();
+    }
     barrier();
     if (s + NS - 1 < nst) issue(std::integral_constant<int, KN>{}, s + NS - 1);
     const float4* slot = slot_of(kc);
@@ -2026,6 +2036,11 @@ hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int
         break;
       case kRingF64x256:
         hipLaunchKernelGGL((k_contract_f32_ringf<1, 4, 2, 2, 8>), g, dim3(256), 0, s, tiles,
+                           p.NrPad, p.kchunk, p.P, p.lineTotal, p.M32, p.B32, p.nrhoSorted,
+                           p.lineOffSorted, p.part);
+        break;
+      case kRingF64x256W8:
+        hipLaunchKernelGGL((k_contract_f32_ringf<2, 4, 1, 2, 8>), g, dim3(512), 0, s, tiles,
                            p.NrPad, p.kchunk, p.P, p.lineTotal, p.M32, p.B32, p.nrhoSorted,
                            p.lineOffSorted, p.part);
         break;
