@@ -838,7 +838,10 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_ring(
 // s = (r / 4) % 4, so that the 16-byte reads of 16 consecutive rows fall in
 // distinct LDS banks.  With 4 bytes a value a slot is small enough for an
 // 8-stage ring (7 stages in flight: measured 0.55 ms against 0.63 ms with 4
-// on the batch workload).
+// on the batch workload).  The workgroup has WR x WC waves (4 or 8); with 8
+// waves of 32 x 64 each, two waves share a SIMD.  A stage that is not a
+// whole number of load rounds for the workgroup ends with a partial round
+// issued by the first RW waves only, and each wave waits on its own count.
 // --------------------------------------------------------------------------
 // Two values rounded to BF16 (nearest even) in one packed conversion: a in
 // the low half, b in the high half.
