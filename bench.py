@@ -320,6 +320,25 @@ def _wpartition_paths(steps):
     return res
 
 
+def _truncated_path(plan, taper, w, out, steps):
+    """The same plan with the 1% truncation step (section 3.1): supports,
+    offsets and the packed cache come back in device memory; the call is
+    timed whole (lines, truncation decision, layout, resample)."""
+    import torch
+    _, sup, offs = plan.generate_truncated(taper, w, 0.01, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.generate_truncated(taper, w, 0.01, out=out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    written = int(offs[-1].item()) * 8
+    sup = sup.cpu().numpy()
+    return {"kernels_per_s": plan.n_planes / wall, "ms_per_step": 1000.0 * wall,
+            "bytes_written": written, "written_GBs": written / wall / 1e9,
+            "support_min_median_max": [int(sup.min()), int(np.median(sup)), int(sup.max())]}
+
+
 def _profile_pass(wl):
     """Kernels for a hardware-counter run: two generate calls of the split path
     and a plain 2 GiB device-to-device copy of known size."""
@@ -405,6 +424,7 @@ def main():
                         "pipeline_chunks": info["chunks"], "contraction_variant": info["variant"],
                         "autotune_ms": info["variant_ms"],
                         "contraction_roofline": _contraction_roofline(plan, wl, stages, "bf16x6")}}
+    paths["bf16x6_truncated_1pct"] = _truncated_path(plan, taper, w, out, args.steps)
     plan.close()
     # every plane computed on its own (no use of K(-w) = conj K(w), section 4.1)
     plan_all = Plan.from_workload(wl, precision="bf16x6", use_mirror=False)

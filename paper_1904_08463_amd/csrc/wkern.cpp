@@ -390,7 +390,7 @@ static wkern_status build_chunks(wkern_plan_s* pl, int want) {
   // resample units: blocks of at most 65536 elements of one plane (multiples
   // of 1024, so every wave chunk starts at a multiple of its size), in chunk
   // order
-  const int64_t unitElems = 65536;
+  const int64_t unitElems = kUnitElems;
   std::vector<ResampleUnit> units;
   pl->chunkU.assign(1, 0);
   for (int c = 0; c < pl->nChunks; ++c) {
@@ -852,9 +852,11 @@ static wkern_status ensure_trunc_scratch(wkern_plan_t plan) {
   wkern_status s;
   if ((s = plan->alloc(&ts.hTrunc, (size_t)g.P, "truncation table")) != WKERN_OK ||
       (s = plan->alloc(&ts.unitStart, (size_t)g.Pall + 1, "truncation table")) != WKERN_OK ||
+      (s = plan->alloc(&ts.unitPlane, (size_t)g.nUnits, "truncation table")) != WKERN_OK ||
       (s = plan->upload(&ts.sortedPos, plan->sortedPosOfCaller, "truncation table")) != WKERN_OK) {
     plan->release(ts.hTrunc);
     plan->release(ts.unitStart);
+    plan->release(ts.unitPlane);
     plan->release(ts.sortedPos);
     return s;
   }

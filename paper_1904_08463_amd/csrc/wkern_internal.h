@@ -78,6 +78,10 @@ inline bool variant_fp32_screen(int precision, int variant) {
   return precision == 0 || variant >= kRingF128x128;
 }
 
+// Resample units: blocks of at most this many consecutive elements of one
+// plane (the full cache's units, and the truncated layout's).
+constexpr int kUnitElems = 65536;
+
 // Planes of a pipeline chunk start at multiples of this (in sorted order),
 // so no contraction column block straddles two chunks.
 constexpr int kChunkAlign = 128;
@@ -141,6 +145,8 @@ struct TruncScratch {
   int32_t* hTrunc;     // [P] truncated half-widths (sorted order)
   int32_t* sortedPos;  // [Pall] caller plane -> sorted index of its source
   int32_t* unitStart;  // [Pall + 1] prefix sums of resample units
+  int32_t* unitPlane;  // [nUnits] plane of each truncated unit (at most the
+                       // untruncated count, supports only shrink)
 };
 hipError_t launch_resample_truncated(const DevPlan& p, const TruncScratch& ts, double frac,
                                      int32_t* supportOut, int64_t* offsetsOut, void* out,

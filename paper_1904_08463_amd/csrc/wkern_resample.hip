@@ -11,103 +11,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------------------
 // Oversampled kernel cache (section 4.4, Algorithm 2), element
-// e = ((fv os + fu) S + b) S + a of a plane.  resample_range below writes a
-// range of elements sample by sample (the truncated layout uses it); the
-// full cache uses k_resample further down, which takes the same FP32 steps
-// per sample with a cheaper position decode.
-//
-// Radius in units of the radial node spacing: t = q sqrt(d2), d2 = X^2 + Y^2
-// (an integer, exact in FP32).  Rounding t itself to FP32 would cost up to
-// ulp(t) ~ 6e-5 nodes at t ~ 1000; instead sqrt(d2) = s + c with s from the
-// hardware reciprocal square root and the Newton correction
-// c = (d2 - s^2) / (2 s) formed with an exact fma residual, and the interval
-// fraction u = (q s - k) + q c keeps ~1e-7 absolute accuracy.  k is the
-// truncation of q s: a value that lands one node early or late only moves
-// u slightly outside [0, 1), where the neighbouring cubic piece agrees.
-// --------------------------------------------------------------------------
-
-// Writes elements [e0, e1) of one plane (its spline intervals already in sc)
-// with coalesced non-temporal 8-byte stores.
-__device__ __forceinline__ void resample_range(const PlaneInfo& pi, int e0, int e1, int os,
-                                               float invOs, float q,
-                                               const float4* __restrict__ sc,
-                                               float2* __restrict__ out) {
-  f32x2* o = (f32x2*)(out + pi.out_off);
-  const int S = pi.S;
-  const int h = pi.h;
-  const int nmax = pi.nrho - 2;
-  const int lane = threadIdx.x & 63;
-  if (S >= 64) {
-    // Each wave takes 64-element chunks wave, wave + 4, ...; the chunk's first
-    // element is decoded once (wave-uniform) and advanced by 256 elements per
-    // step; within a chunk a row boundary is crossed at most once.
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int e = e0 + 64 * wave;
-    int R = e / S;
-    int a0 = e - R * S;
-    int F = R / S;
-    int b0 = R - F * S;
-    int fv0 = F / os;
-    int fu0 = F - fv0 * os;
-    const int stepA = 256 % S;
-    const int stepR = 256 / S;
-    for (; e < e1; e += 256) {
-      if (e + lane < e1) {
-        int a = a0 + lane;
-        int b = b0, fu = fu0, fv = fv0;
-        if (a >= S) {
-          a -= S;
-          b += 1;
-          if (b == S) {
-            b = 0;
-            fu += 1;
-            if (fu == os) {
-              fu = 0;
-              fv += 1;
-            }
-          }
-        }
-        const int X = os * (a - h) - fu;
-        const int Y = os * (b - h) - fv;
-        f32x2 v = cache_value(X, Y, pi.lim, q, nmax, sc);
-        v.y = pi.conj ? -v.y : v.y;
-        __builtin_nontemporal_store(v, o + e + lane);
-      }
-      a0 += stepA;
-      int c = stepR;
-      if (a0 >= S) {
-        a0 -= S;
-        c += 1;
-      }
-      b0 += c;
-      if (b0 >= S) {
-        b0 -= S;
-        fu0 += 1;
-        if (fu0 == os) {
-          fu0 = 0;
-          fv0 += 1;
-        }
-      }
-    }
-  } else {
-    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
-      int a, b, fu;
-      const int R = div_small(e, S, pi.invS, a);
-      const int F = div_small(R, S, pi.invS, b);
-      const int fv = div_small(F, os, invOs, fu);
-      const int X = os * (a - h) - fu;
-      const int Y = os * (b - h) - fv;
-      f32x2 v = cache_value(X, Y, pi.lim, q, nmax, sc);
-      v.y = pi.conj ? -v.y : v.y;
-      __builtin_nontemporal_store(v, o + e);
-    }
-  }
-}
-
-// --------------------------------------------------------------------------
-// Full cache: a workgroup of 256 threads per resample unit (at most 65536
-// consecutive elements of one plane, starting at a multiple of 512), the
-// plane's spline intervals staged in LDS once.  Each wave takes 128
+// e = ((fv os + fu) S + b) S + a of a plane.  Full cache: a workgroup of 256
+// threads per resample unit (at most 65536 consecutive elements of one
+// plane, starting at a multiple of 512), the plane's spline intervals staged
+// in LDS once; the truncated layout writes its units the same way.  Each wave takes 128
 // consecutive elements per step (waves interleaved, 512 per step) and each
 // lane two neighbours, written with one 16-byte store: on this chip that
 // store pattern writes the cache about 8% faster than one 8-byte store per
@@ -215,6 +122,69 @@ __device__ __forceinline__ void resample_rows(int e, int e1, RowPos p0, int S, i
   }
 }
 
+// Elements [e0, e1) of plane pi (its spline intervals in sc), by the block's
+// 4 waves; e0 is even.
+template <bool kQ1>
+__device__ __forceinline__ void resample_unit(const PlaneInfo& pi, int e0, int e1, int os,
+                                              float invOs, uint32_t magicOs, int shiftOs,
+                                              float q, const float4* __restrict__ sc,
+                                              float2* __restrict__ out) {
+  const int S = pi.S, h = pi.h, lim = pi.lim;
+  const int nmax = pi.nrho - 2;
+  const float hq = 0.5f * q;
+  const uint32_t sgn = pi.conj ? 0x80000000u : 0u;
+  const int off = 2 * (threadIdx.x & 63);
+  f32x2* const o = (f32x2*)(out + pi.out_off);
+  const bool al16 = ((uintptr_t)o & 15) == 0;
+  if (S >= 64) {
+    // scalar decode of the first element of the wave's first chunk
+    const int ch = S >= 128 ? 256 : 128;
+    const int w0 = e0 + ch * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int R = (int)(__umulhi((uint32_t)w0, pi.magicS) >> pi.shiftS);
+    const int F = (int)(__umulhi((uint32_t)R, pi.magicS) >> pi.shiftS);
+    const int fv = os == 1 ? F : (int)(__umulhi((uint32_t)F, magicOs) >> shiftOs);
+    const RowPos p0{w0 - R * S, R - F * S, F - fv * os, fv};
+    if (S >= 128)
+      resample_rows<256, kQ1>(w0, e1, p0, S, h, os, lim, q, hq, nmax, sc, sgn, off, al16, o);
+    else
+      resample_rows<128, kQ1>(w0, e1, p0, S, h, os, lim, q, hq, nmax, sc, sgn, off, al16, o);
+  } else {
+    const int e = e0 + 128 * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int ee = e + off; ee - off < e1; ee += 512) {
+      // the pair's first element by division, the second by one column step
+      // with the carries into row, fu and fv
+      int a, b, fu;
+      const int R = div_small(ee, S, pi.invS, a);
+      const int F = div_small(R, S, pi.invS, b);
+      int fv = div_small(F, os, invOs, fu);
+      const int X0 = os * (a - h) - fu;
+      const int Y0 = os * (b - h) - fv;
+      if (++a == S) {
+        a = 0;
+        if (++b == S) {
+          b = 0;
+          if (++fu == os) {
+            fu = 0;
+            ++fv;
+          }
+        }
+      }
+      const int X1 = os * (a - h) - fu;
+      const int Y1 = os * (b - h) - fv;
+      const f32x2 v0 = unit_value<kQ1>(X0 * X0 + Y0 * Y0, lim, q, hq, nmax, sc, sgn);
+      const f32x2 v1 = unit_value<kQ1>(X1 * X1 + Y1 * Y1, lim, q, hq, nmax, sc, sgn);
+      f32x2* p = o + ee;
+      if (ee + 1 < e1 && al16) {
+        f32x4 w4 = {v0.x, v0.y, v1.x, v1.y};
+        *(f32x4*)p = w4;
+      } else {
+        if (ee < e1) p[0] = v0;
+        if (ee + 1 < e1) p[1] = v1;
+      }
+    }
+  }
+}
+
 template <bool kQ1>
 __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict__ units,
                                                   const PlaneInfo* __restrict__ planes,
@@ -227,68 +197,27 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
   extern __shared__ float4 sc[];  // [nrho][2]
   const ResampleUnit u = units[blockIdx.x];
   const PlaneInfo pi = planes[u.p];
-  const int n = pi.nrho;
-  const int nmax = n - 2;
+  const int nmax = pi.nrho - 2;
   const float4* src = coef + (size_t)pi.line_off * 2;
   for (int i = threadIdx.x; i < 2 * nmax + 2; i += 256) sc[i] = src[i];
   if (threadIdx.x < 2) sc[2 * nmax + 2 + threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
   __syncthreads();
-  const int S = pi.S, h = pi.h, lim = pi.lim;
-  const float hq = 0.5f * q;
-  const uint32_t sgn = pi.conj ? 0x80000000u : 0u;
-  const int off = 2 * (threadIdx.x & 63);
-  f32x2* const o = (f32x2*)(out + pi.out_off);
-  const bool al16 = ((uintptr_t)o & 15) == 0;
-  if (S >= 64) {
-    // scalar decode of the first element of the wave's first chunk
-    const int ch = S >= 128 ? 256 : 128;
-    const int e0 = u.e0 + ch * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int R = (int)(__umulhi((uint32_t)e0, pi.magicS) >> pi.shiftS);
-    const int F = (int)(__umulhi((uint32_t)R, pi.magicS) >> pi.shiftS);
-    const int fv = os == 1 ? F : (int)(__umulhi((uint32_t)F, magicOs) >> shiftOs);
-    const RowPos p0{e0 - R * S, R - F * S, F - fv * os, fv};
-    if (S >= 128)
-      resample_rows<256, kQ1>(e0, u.e1, p0, S, h, os, lim, q, hq, nmax, sc, sgn, off, al16, o);
-    else
-      resample_rows<128, kQ1>(e0, u.e1, p0, S, h, os, lim, q, hq, nmax, sc, sgn, off, al16, o);
-  } else {
-    const int e = u.e0 + 128 * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int ee = e + off; ee - off < u.e1; ee += 512) {
-      auto d2_of = [&](int x) {
-        int a, b, fu;
-        const int R = div_small(x, S, pi.invS, a);
-        const int F = div_small(R, S, pi.invS, b);
-        const int fv = div_small(F, os, invOs, fu);
-        const int X = os * (a - h) - fu;
-        const int Y = os * (b - h) - fv;
-        return X * X + Y * Y;
-      };
-      const f32x2 v0 = unit_value<kQ1>(d2_of(ee), lim, q, hq, nmax, sc, sgn);
-      const f32x2 v1 = unit_value<kQ1>(d2_of(ee + 1), lim, q, hq, nmax, sc, sgn);
-      f32x2* p = o + ee;
-      if (ee + 1 < u.e1 && al16) {
-        f32x4 w4 = {v0.x, v0.y, v1.x, v1.y};
-        *(f32x4*)p = w4;
-      } else {
-        if (ee < u.e1) p[0] = v0;
-        if (ee + 1 < u.e1) p[1] = v1;
-      }
-    }
-  }
+  resample_unit<kQ1>(pi, u.e0, u.e1, os, invOs, magicOs, shiftOs, q, sc, out);
 }
 
 // Truncated layout (section 3.1, Algorithm 2): one block of 1024 threads.
 // Plane p (caller order) takes the half-width its source line was truncated
 // to; writes supports, the exclusive prefix sums of os^2 S^2 (offsets) and
-// of the per-plane resample units (unitStart, units of kUnitElems).
-constexpr int kUnitElems = 65536;
+// of the per-plane resample units (unitStart, units of kUnitElems), and the
+// plane of every unit (unitPlane).
 
 __global__ __launch_bounds__(1024) void k_trunc_layout(int Pall, int os,
                                                        const int32_t* __restrict__ hSorted,
                                                        const int32_t* __restrict__ sortedPos,
                                                        int32_t* __restrict__ supportOut,
                                                        int64_t* __restrict__ offsetsOut,
-                                                       int32_t* __restrict__ unitStart) {
+                                                       int32_t* __restrict__ unitStart,
+                                                       int32_t* __restrict__ unitPlane) {
   __shared__ int64_t sBytes[1024];
   __shared__ int32_t sUnits[1024];
   __shared__ int64_t carryB;
@@ -326,7 +255,9 @@ __global__ __launch_bounds__(1024) void k_trunc_layout(int Pall, int os,
     }
     if (p < Pall) {
       offsetsOut[p] = carryB + sBytes[threadIdx.x] - n;
-      unitStart[p] = carryU + sUnits[threadIdx.x] - nu;
+      const int32_t u0 = carryU + sUnits[threadIdx.x] - nu;
+      unitStart[p] = u0;
+      for (int32_t k = 0; k < nu; ++k) unitPlane[u0 + k] = p;
     }
     __syncthreads();
     if (threadIdx.x == 1023) {
@@ -342,24 +273,23 @@ __global__ __launch_bounds__(1024) void k_trunc_layout(int Pall, int os,
 }
 
 // Resample of a truncated layout: a fixed grid walks the units; unit u
-// belongs to the plane found by binary search in unitStart.
+// belongs to plane unitPlane[u].  The plane's entry takes its truncated
+// width (and the divisors for it), and the unit is written as in the full
+// cache.
+template <bool kQ1>
 __global__ __launch_bounds__(256) void k_resample_trunc(int Pall, const PlaneInfo* __restrict__ planes,
                                                         const int32_t* __restrict__ supportOut,
                                                         const int64_t* __restrict__ offsetsOut,
                                                         const int32_t* __restrict__ unitStart,
+                                                        const int32_t* __restrict__ unitPlane,
                                                         const float4* __restrict__ coef, int os,
-                                                        float invOs, float q,
-                                                        float2* __restrict__ out) {
+                                                        float invOs, uint32_t magicOs, int shiftOs,
+                                                        float q, float2* __restrict__ out) {
   extern __shared__ float4 sc[];
   const int total = unitStart[Pall];
+  const int qi = (int)q;
   for (int u = blockIdx.x; u < total; u += gridDim.x) {
-    int lo = 0, hi = Pall - 1;  // last p with unitStart[p] <= u
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (unitStart[mid] <= u) lo = mid;
-      else hi = mid - 1;
-    }
-    const int p = lo;
+    const int p = unitPlane[u];
     PlaneInfo pi = planes[p];
     const int S = supportOut[p];
     pi.S = S;
@@ -367,14 +297,22 @@ __global__ __launch_bounds__(256) void k_resample_trunc(int Pall, const PlaneInf
     pi.lim = (os * pi.h) * (os * pi.h);
     pi.invS = 1.0f / (float)S;
     pi.out_off = offsetsOut[p];
+    magic_div24((uint32_t)(S > 2 ? S : 2), pi.magicS, pi.shiftS);
     const int n = os * os * S * S;
     const int e0 = (u - unitStart[p]) * kUnitElems;
     const int e1 = min(n, e0 + kUnitElems);
+    const int nmax = pi.nrho - 2;
+    // a sample inside the truncated support has q sqrt(d2) <= q os h, so it
+    // reads an interval up to q os h; the line runs to the planned support,
+    // and only its first intervals are staged (plus the zero interval
+    // nmax + 1 for the samples outside)
+    const int kTop = min(nmax, qi * os * pi.h + 1);
     __syncthreads();  // the previous unit is done with sc
     const float4* src = coef + (size_t)pi.line_off * 2;
-    for (int k = threadIdx.x; k < pi.nrho * 2; k += 256) sc[k] = src[k];
+    for (int k = threadIdx.x; k < 2 * kTop + 2; k += 256) sc[k] = src[k];
+    if (threadIdx.x < 2) sc[2 * nmax + 2 + threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
-    resample_range(pi, e0, e1, os, invOs, q, sc, out);
+    resample_unit<kQ1>(pi, e0, e1, os, invOs, magicOs, shiftOs, q, sc, out);
   }
 }
 
@@ -402,12 +340,20 @@ hipError_t launch_resample_truncated(const DevPlan& p, const TruncScratch& ts, d
   hipError_t e = launch_spline(p, 0, p.P, s, frac, ts.hTrunc);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_trunc_layout, dim3(1), dim3(1024), 0, s, p.Pall, p.os, ts.hTrunc,
-                     ts.sortedPos, supportOut, offsetsOut, ts.unitStart);
+                     ts.sortedPos, supportOut, offsetsOut, ts.unitStart, ts.unitPlane);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t shm = (size_t)2 * p.nrhoMax * sizeof(float4);
-  hipLaunchKernelGGL(k_resample_trunc, dim3(2048), dim3(256), shm, s, p.Pall, p.planes, supportOut,
-                     offsetsOut, ts.unitStart, p.coef, p.os, 1.0f / (float)p.os, (float)p.q,
-                     (float2*)out);
+  uint32_t mOs = 0;
+  int32_t shOs = 0;
+  if (p.os >= 2) magic_div24((uint32_t)p.os, mOs, shOs);
+  if (p.q == 1)
+    hipLaunchKernelGGL(k_resample_trunc<true>, dim3(2048), dim3(256), shm, s, p.Pall, p.planes,
+                       supportOut, offsetsOut, ts.unitStart, ts.unitPlane, p.coef, p.os, 1.0f / (float)p.os,
+                       mOs, shOs, 1.0f, (float2*)out);
+  else
+    hipLaunchKernelGGL(k_resample_trunc<false>, dim3(2048), dim3(256), shm, s, p.Pall, p.planes,
+                       supportOut, offsetsOut, ts.unitStart, ts.unitPlane, p.coef, p.os, 1.0f / (float)p.os,
+                       mOs, shOs, (float)p.q, (float2*)out);
   return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // of cache elements (shared by the host plan code and the kernels).
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace wkern {
@@ -25,7 +26,7 @@ struct PlaneInfo {
 // x / d = umulhi(x, m) >> sh.  With L = max(32, 24 + ceil(log2 d)) and
 // m = ceil(2^L / d), x m / 2^L exceeds x / d by less than x / 2^L < 2^-(L-24)
 // <= 1 / d, which cannot carry it past the next integer.
-inline void magic_div24(uint32_t d, uint32_t& m, int32_t& sh) {
+__host__ __device__ inline void magic_div24(uint32_t d, uint32_t& m, int32_t& sh) {
   int l = 0;
   while ((1u << l) < d) ++l;
   const int L = l + 24 > 32 ? l + 24 : 32;
