@@ -577,6 +577,7 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
     return s;
 
   WK_HIP(prepare_kernels(g), "kernel attributes");
+  WK_HIP(prepare_resample_kernels(g), "kernel attributes");
   WK_HIP(launch_hankel_matrix(g, nullptr), "HT matrix launch");
   WK_HIP(hipDeviceSynchronize(), "HT matrix");
 

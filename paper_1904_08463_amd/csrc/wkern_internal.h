@@ -152,6 +152,8 @@ hipError_t launch_resample_truncated(const DevPlan& p, const TruncScratch& ts, d
                                      int32_t* supportOut, int64_t* offsetsOut, void* out,
                                      hipStream_t s);
 hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStream_t s);
+// Kernel attributes of the resample kernels that depend on the plan.
+hipError_t prepare_resample_kernels(const DevPlan& p);
 hipError_t launch_lines_out(const DevPlan& p, void* lines, hipStream_t s);
 
 // Plane supports after wkern_prepare_lines (truncated when hTrunc is given).

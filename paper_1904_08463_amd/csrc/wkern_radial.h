@@ -25,7 +25,7 @@ __device__ __forceinline__ void radial_pos(int d2, float q, int nmax, int& k, fl
 // (off by at most one) and one integer correction.
 __device__ __forceinline__ int div_small(int n, int d, float inv, int& rem) {
   int qt = (int)((float)n * inv);
-  int r = n - qt * d;
+  int r = n - __mul24(qt, d);  // 0 <= qt, d < 2^24: the 24-bit multiply is exact
   if (r < 0) {
     qt -= 1;
     r += d;

@@ -171,8 +171,10 @@ __device__ __forceinline__ void resample_unit(const PlaneInfo& pi, int e0, int e
       }
       const int X1 = os * (a - h) - fu;
       const int Y1 = os * (b - h) - fv;
-      const f32x2 v0 = unit_value<kQ1>(X0 * X0 + Y0 * Y0, lim, q, hq, nmax, sc, sgn);
-      const f32x2 v1 = unit_value<kQ1>(X1 * X1 + Y1 * Y1, lim, q, hq, nmax, sc, sgn);
+      const f32x2 v0 =
+          unit_value<kQ1>(__mul24(X0, X0) + __mul24(Y0, Y0), lim, q, hq, nmax, sc, sgn);
+      const f32x2 v1 =
+          unit_value<kQ1>(__mul24(X1, X1) + __mul24(Y1, Y1), lim, q, hq, nmax, sc, sgn);
       f32x2* p = o + ee;
       if (ee + 1 < e1 && al16) {
         f32x4 w4 = {v0.x, v0.y, v1.x, v1.y};
@@ -209,8 +211,10 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
 // Plane p (caller order) takes the half-width its source line was truncated
 // to; writes supports, the exclusive prefix sums of os^2 S^2 (offsets) and
 // of the per-plane resample units (unitStart, units of kUnitElems), and the
-// plane of every unit (unitPlane).
-
+// plane of every unit (unitPlane).  Thread t sums a run of consecutive
+// planes, one scan over the 1024 run totals gives each run its start, and
+// the thread then writes its planes' entries (integer sums: the same result
+// in any order).
 __global__ __launch_bounds__(1024) void k_trunc_layout(int Pall, int os,
                                                        const int32_t* __restrict__ hSorted,
                                                        const int32_t* __restrict__ sortedPos,
@@ -220,55 +224,54 @@ __global__ __launch_bounds__(1024) void k_trunc_layout(int Pall, int os,
                                                        int32_t* __restrict__ unitPlane) {
   __shared__ int64_t sBytes[1024];
   __shared__ int32_t sUnits[1024];
-  __shared__ int64_t carryB;
-  __shared__ int32_t carryU;
-  if (threadIdx.x == 0) {
-    carryB = 0;
-    carryU = 0;
-  }
+  extern __shared__ uint16_t sWidth[];  // [Pall] truncated widths (<= 4095)
+  const int t = (int)threadIdx.x;
+#pragma unroll 8
+  for (int p = t; p < Pall; p += 1024) sWidth[p] = (uint16_t)(2 * hSorted[sortedPos[p]] + 1);
   __syncthreads();
-  for (int base = 0; base < Pall; base += 1024) {
-    const int p = base + (int)threadIdx.x;
-    int64_t n = 0;
-    int32_t nu = 0;
-    if (p < Pall) {
-      const int S = 2 * hSorted[sortedPos[p]] + 1;
-      supportOut[p] = S;
-      n = (int64_t)os * os * S * S;
-      nu = (int32_t)((n + kUnitElems - 1) / kUnitElems);
-    }
-    sBytes[threadIdx.x] = n;
-    sUnits[threadIdx.x] = nu;
-    __syncthreads();
-    // inclusive scan (Hillis-Steele) in a fixed order
-    for (int d = 1; d < 1024; d <<= 1) {
-      int64_t tb = 0;
-      int32_t tu = 0;
-      if ((int)threadIdx.x >= d) {
-        tb = sBytes[threadIdx.x - d];
-        tu = sUnits[threadIdx.x - d];
-      }
-      __syncthreads();
-      sBytes[threadIdx.x] += tb;
-      sUnits[threadIdx.x] += tu;
-      __syncthreads();
-    }
-    if (p < Pall) {
-      offsetsOut[p] = carryB + sBytes[threadIdx.x] - n;
-      const int32_t u0 = carryU + sUnits[threadIdx.x] - nu;
-      unitStart[p] = u0;
-      for (int32_t k = 0; k < nu; ++k) unitPlane[u0 + k] = p;
+  const int per = (Pall + 1023) / 1024;
+  const int p0 = min(Pall, t * per), p1 = min(Pall, p0 + per);
+  auto width = [&](int p) { return (int)sWidth[p]; };
+  int64_t nb = 0;
+  int32_t nu = 0;
+  for (int p = p0; p < p1; ++p) {
+    const int S = width(p);
+    const int64_t n = (int64_t)os * os * S * S;
+    nb += n;
+    nu += (int32_t)((n + kUnitElems - 1) / kUnitElems);
+  }
+  sBytes[t] = nb;
+  sUnits[t] = nu;
+  __syncthreads();
+  // inclusive scan (Hillis-Steele) over the run totals
+  for (int d = 1; d < 1024; d <<= 1) {
+    int64_t tb = 0;
+    int32_t tu = 0;
+    if (t >= d) {
+      tb = sBytes[t - d];
+      tu = sUnits[t - d];
     }
     __syncthreads();
-    if (threadIdx.x == 1023) {
-      carryB += sBytes[1023];
-      carryU += sUnits[1023];
-    }
+    sBytes[t] += tb;
+    sUnits[t] += tu;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    offsetsOut[Pall] = carryB;
-    unitStart[Pall] = carryU;
+  int64_t cb = sBytes[t] - nb;
+  int32_t cu = sUnits[t] - nu;
+  for (int p = p0; p < p1; ++p) {
+    const int S = width(p);
+    const int64_t n = (int64_t)os * os * S * S;
+    const int32_t k = (int32_t)((n + kUnitElems - 1) / kUnitElems);
+    supportOut[p] = S;
+    offsetsOut[p] = cb;
+    unitStart[p] = cu;
+    for (int32_t i = 0; i < k; ++i) unitPlane[cu + i] = p;
+    cb += n;
+    cu += k;
+  }
+  if (t == 1023) {
+    offsetsOut[Pall] = sBytes[1023];
+    unitStart[Pall] = sUnits[1023];
   }
 }
 
@@ -334,12 +337,24 @@ hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStrea
   return hipGetLastError();
 }
 
+hipError_t prepare_resample_kernels(const DevPlan& p) {
+  // the layout kernel holds every plane's width in LDS (2 bytes each) beside
+  // 12 KB of scan arrays; above 64 KiB in all it must be enabled before any
+  // launch or stream capture
+  const size_t shmW = (size_t)p.Pall * sizeof(uint16_t);
+  if (shmW > 65536 - 12288)
+    return hipFuncSetAttribute((const void*)k_trunc_layout,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmW);
+  return hipSuccess;
+}
+
 hipError_t launch_resample_truncated(const DevPlan& p, const TruncScratch& ts, double frac,
                                      int32_t* supportOut, int64_t* offsetsOut, void* out,
                                      hipStream_t s) {
   hipError_t e = launch_spline(p, 0, p.P, s, frac, ts.hTrunc);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_trunc_layout, dim3(1), dim3(1024), 0, s, p.Pall, p.os, ts.hTrunc,
+  const size_t shmW = (size_t)p.Pall * sizeof(uint16_t);
+  hipLaunchKernelGGL(k_trunc_layout, dim3(1), dim3(1024), shmW, s, p.Pall, p.os, ts.hTrunc,
                      ts.sortedPos, supportOut, offsetsOut, ts.unitStart, ts.unitPlane);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t shm = (size_t)2 * p.nrhoMax * sizeof(float4);
@@ -347,11 +362,11 @@ hipError_t launch_resample_truncated(const DevPlan& p, const TruncScratch& ts, d
   int32_t shOs = 0;
   if (p.os >= 2) magic_div24((uint32_t)p.os, mOs, shOs);
   if (p.q == 1)
-    hipLaunchKernelGGL(k_resample_trunc<true>, dim3(2048), dim3(256), shm, s, p.Pall, p.planes,
+    hipLaunchKernelGGL(k_resample_trunc<true>, dim3(p.nUnits), dim3(256), shm, s, p.Pall, p.planes,
                        supportOut, offsetsOut, ts.unitStart, ts.unitPlane, p.coef, p.os, 1.0f / (float)p.os,
                        mOs, shOs, 1.0f, (float2*)out);
   else
-    hipLaunchKernelGGL(k_resample_trunc<false>, dim3(2048), dim3(256), shm, s, p.Pall, p.planes,
+    hipLaunchKernelGGL(k_resample_trunc<false>, dim3(p.nUnits), dim3(256), shm, s, p.Pall, p.planes,
                        supportOut, offsetsOut, ts.unitStart, ts.unitPlane, p.coef, p.os, 1.0f / (float)p.os,
                        mOs, shOs, (float)p.q, (float2*)out);
   return hipGetLastError();

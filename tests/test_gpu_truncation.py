@@ -111,3 +111,29 @@ def test_truncated_rejects_bad_arguments():
     with pytest.raises(WkernError):
         plan.generate_truncated(taper, w, 0.01, out=small)
     plan.close()
+
+
+def test_truncated_layout_many_planes():
+    """30000 planes: the layout kernel then holds 58 KB of plane widths in
+    LDS (above the default 64 KiB with its scan arrays).  The first 1000
+    planes must get the supports a 1000-plane plan gives them, and the
+    offsets must be the prefix sums of os^2 S^2 of the returned supports."""
+    from paper_1904_08463_amd import Plan
+    base = W.plain()
+    n_big, n_small, os_, s_max = 30000, 1000, 2, 15
+    rng = np.random.default_rng(5)
+    w = np.ascontiguousarray(rng.uniform(0.0, 1000.0, n_big))
+    taper = torch.from_numpy(base.taper).cuda()
+    print(f"case truncated layout planes={n_big}", flush=True)
+    res = {}
+    for n in (n_big, n_small):
+        plan = Plan(base.image_size, base.cellsize, base.n_radial, os_, np.full(n, s_max), s_max,
+                    precision="fp32")
+        _, sup, offs = plan.generate_truncated(taper, torch.from_numpy(w[:n]).cuda(), 0.01)
+        res[n] = (sup.cpu().numpy(), offs.cpu().numpy())
+        plan.close()
+    sup_b, offs_b = res[n_big]
+    assert np.array_equal(sup_b[:n_small], res[n_small][0])
+    assert np.all((sup_b % 2 == 1) & (sup_b >= 1) & (sup_b <= s_max))
+    expect = np.concatenate([[0], np.cumsum(os_ * os_ * sup_b.astype(np.int64) ** 2)])
+    assert np.array_equal(offs_b, expect)
