@@ -320,6 +320,18 @@ def _wpartition_paths(steps):
     return res
 
 
+def _guarded(fn, *args, name=None):
+    """Run an auxiliary measurement; a failure is reported in its entry (as
+    {name: {"error": ...}} for the ones that return several paths) instead of
+    taking the headline line down with it."""
+    try:
+        return fn(*args)
+    except Exception as exc:  # reported, not hidden
+        err = {"error": f"{type(exc).__name__}: {exc}"}
+        print(f"bench: {fn.__name__} failed: {err['error']}", file=sys.stderr, flush=True)
+        return {name: err} if name else err
+
+
 def _truncated_path(plan, taper, w, out, steps):
     """The same plan with the 1% truncation step (section 3.1): supports,
     offsets and the packed cache come back in device memory; the call is
@@ -424,7 +436,7 @@ def main():
                         "pipeline_chunks": info["chunks"], "contraction_variant": info["variant"],
                         "autotune_ms": info["variant_ms"],
                         "contraction_roofline": _contraction_roofline(plan, wl, stages, "bf16x6")}}
-    paths["bf16x6_truncated_1pct"] = _truncated_path(plan, taper, w, out, args.steps)
+    paths["bf16x6_truncated_1pct"] = _guarded(_truncated_path, plan, taper, w, out, args.steps)
     plan.close()
     # every plane computed on its own (no use of K(-w) = conj K(w), section 4.1)
     plan_all = Plan.from_workload(wl, precision="bf16x6", use_mirror=False)
@@ -448,12 +460,13 @@ def main():
         plan32.close()
 
     if not args.skip_fft:
-        paths.update(_fft_paths(wl, taper, w, out, args.fft_steps))
+        paths.update(_guarded(_fft_paths, wl, taper, w, out, args.fft_steps, name="fft2d"))
     if not args.skip_projslice:
-        paths.update(_projslice_paths(wl, taper, w, out, args.steps))
-    paths["wpartition"] = _wpartition_paths(args.steps)
-    paths["gridding_paper_setting"] = _gridding_paths(args.steps)
-    paths["gradient"] = _gradient_path(args.steps)
+        paths.update(_guarded(_projslice_paths, wl, taper, w, out, args.steps,
+                              name="projection_slice"))
+    paths["wpartition"] = _guarded(_wpartition_paths, args.steps)
+    paths["gridding_paper_setting"] = _guarded(_gridding_paths, args.steps)
+    paths["gradient"] = _guarded(_gradient_path, args.steps)
 
     line = {
         "metric": "w-kernels/sec at <=1e-6 rel err (split-BF16 Hankel; FP32 Hankel beside it)",
@@ -479,7 +492,7 @@ def main():
         "paths": paths,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = _cpu_baseline(wl, args.cpu_stride)
+        line["cpu_baseline"] = _guarded(_cpu_baseline, wl, args.cpu_stride)
     print(json.dumps(line), flush=True)
 
 
