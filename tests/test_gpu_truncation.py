@@ -137,3 +137,40 @@ def test_truncated_layout_many_planes():
     assert np.all((sup_b % 2 == 1) & (sup_b >= 1) & (sup_b <= s_max))
     expect = np.concatenate([[0], np.cumsum(os_ * os_ * sup_b.astype(np.int64) ** 2)])
     assert np.array_equal(offs_b, expect)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("sig,os_,q", [(0.0035, 3, 1), (0.004, 8, 2), (0.007, 8, 1)])
+def test_truncated_support_between_cells(precision, sig, os_, q):
+    """Gaussian tapers whose 1% node k* is not a multiple of q os (the
+    closed-form cases of the oracle's truncation pins): the device must round
+    the half-width up, h = ceil(k* / (q os)), exactly as the oracle does;
+    w = 0 and small |w| (still monotone, same k*) and a clamped plane."""
+    import math
+    from paper_1904_08463_amd import Plan
+    base = W.plain(n_radial=2048)
+    tau = np.ascontiguousarray(W.sample_taper(W.gaussian_taper(sig), 2048, base.r_max).astype(np.float32))
+    w = np.array([0.0, 1.0, -1.0, 2.0], dtype=np.float64)
+    sup_plan = np.array([63, 63, 63, 9], dtype=np.int32)  # the last plane is clamped
+    print(f"case truncation between cells sig={sig} os={os_} q={q} {precision}", flush=True)
+    plan = Plan(base.image_size, base.cellsize, 2048, os_, sup_plan, 63, radial_refine=q,
+                precision=precision)
+    out, sup, offs = plan.generate_truncated(torch.from_numpy(tau).cuda(),
+                                             torch.from_numpy(w).cuda(), 0.01)
+    out, sup, offs = out.cpu().numpy(), sup.cpu().numpy(), offs.cpu().numpy()
+    geo = H.geometry(base.image_size, base.cellsize, 2048, os_, q)
+    k_star = math.floor(math.sqrt(math.log(100.0) / (2 * math.pi ** 2 * sig ** 2)) / geo.drho)
+    assert k_star % (q * os_) != 0
+    h_expect = -(-k_star // (q * os_))
+    for p in range(len(w)):
+        caches, s_ref, _ = H.generate_truncated(base.image_size, base.cellsize, 2048, os_, tau, w,
+                                                int(sup_plan[p]), radial_refine=q, planes=[p])
+        assert sup[p] == s_ref[0], (p, sup[p], s_ref[0])
+        if p < 3:
+            assert sup[p] == 2 * h_expect + 1, (p, sup[p], h_expect)
+        else:
+            assert sup[p] == 9
+        got = out[offs[p]:offs[p + 1]].reshape(caches[0].shape)
+        e = float(np.max(np.abs(got - caches[0])) / np.max(np.abs(caches[0])))
+        assert e <= GATE[precision], (p, e)
+    plan.close()

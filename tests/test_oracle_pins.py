@@ -365,6 +365,74 @@ def test_truncation_gaussian_closed_form():
     assert 1 < sup[0] < 63
 
 
+# (sigma, os, q): the closed-form 1% node k1 lies well inside a node interval
+# (fractional part between 0.2 and 0.8) and floor(k1) is not a multiple of
+# q os, so rounding the half-width up or down, or stopping at the first node
+# below the threshold instead of the last one at or above it, give different
+# supports.
+_TRUNC_CASES = [(0.0035, 3, 1), (0.0045, 3, 2), (0.005, 4, 1), (0.004, 8, 2),
+                (0.005, 8, 2), (0.007, 8, 1)]
+
+
+@pytest.mark.parametrize("sig,os_,q", _TRUNC_CASES)
+def test_truncation_gaussian_node_between_cells(sig, os_, q):
+    """w = 0 and a Gaussian taper of width sig, far inside the disc: the
+    line is K(rho) = 2 pi sig^2 exp(-2 pi^2 sig^2 rho^2) (decreasing), so the
+    last node at or above 1% of the peak is k* = floor(k1), k1 = rho_1 / drho
+    with rho_1 = sqrt(ln 100 / (2 pi^2 sig^2)).  The circular support must
+    reach rho_{k*}: the smallest half-width h with q os h >= k*
+    (section 3.1, Algorithm 2: the kernel is cut where it falls below the
+    fraction of its peak, so nothing at or above it is cut)."""
+    wl = W.plain(n_radial=2048)
+    tau = W.sample_taper(W.gaussian_taper(sig), 2048, wl.r_max)
+    geo = H.geometry(wl.image_size, wl.cellsize, 2048, os_, q)
+    k1 = math.sqrt(math.log(100.0) / (2 * math.pi ** 2 * sig ** 2)) / geo.drho
+    k_star = math.floor(k1)
+    assert 0.2 < k1 - k_star < 0.8 and k_star % (q * os_) != 0  # the case discriminates
+    _, sup, lines = H.generate_truncated(wl.image_size, wl.cellsize, 2048, os_, tau, [0.0], 63,
+                                         radial_refine=q)
+    # the discrete line agrees with the closed form well below the margin
+    amp = np.abs(lines[0])
+    assert amp[k_star] >= 0.01 * amp.max() > amp[k_star + 1]
+    h = (int(sup[0]) - 1) // 2
+    assert q * os_ * h >= k_star           # the support reaches rho_{k*}
+    assert q * os_ * (h - 1) < k_star      # and is the smallest that does
+    assert 1 < sup[0] < 63
+
+
+def test_truncation_clamped_at_planned_support():
+    """A kernel wider than the planned maximum: the line (computed for the
+    maximum, q os h_max + 4 nodes) stays above 1% to its last node, so the
+    rule asks for more than h_max and the support is clamped to S_max."""
+    sig, os_, s_max = 0.0035, 4, 21          # closed-form k* = 55, line has 44 nodes
+    wl = W.plain(n_radial=2048)
+    tau = W.sample_taper(W.gaussian_taper(sig), 2048, wl.r_max)
+    _, sup, lines = H.generate_truncated(wl.image_size, wl.cellsize, 2048, os_, tau, [0.0], s_max)
+    amp = np.abs(lines[0])
+    assert len(amp) == os_ * (s_max - 1) // 2 + 4 and amp[-1] >= 0.01 * amp.max()
+    assert int(sup[0]) == s_max
+    # with a wider plan the same kernel gets its own (narrower than 2 h + 3) support
+    _, sup_w, _ = H.generate_truncated(wl.image_size, wl.cellsize, 2048, os_, tau, [0.0], 63)
+    assert s_max < int(sup_w[0]) < 63
+
+
+@pytest.mark.parametrize("line,frac,os_,q,h_max,h_expect", [
+    # dips below 1% at node 2 and comes back above at node 4: the last node
+    # at or above the threshold decides (k* = 4), h = ceil(4 / 3) = 2
+    ([1.0, 0.5, 0.001, 0.002, 0.05, 0.003, 0.0, 0.0, 0.0], 0.01, 3, 1, 3, 2),
+    # a node exactly at the threshold counts; amplitude of a complex value
+    ([1.0, 0.2, 0.1, 0.006 + 0.008j, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0], 0.01, 2, 1, 4, 2),
+    # the peak need not be at rho = 0; negative values count by magnitude
+    ([0.3, -2.0, 0.9, 0.05, -0.021, 0.025, 0.019, 0.0, 0.0, 0.0, 0.0], 0.01, 2, 2, 2, 2),
+    # k* = 9 at the end of a 10-node line asks for ceil(9 / 2) = 5 > h_max = 4
+    ([1.0] * 10, 0.01, 2, 1, 4, 4),
+    # only the peak is above: k* = 0 gives a single-pixel kernel
+    ([1.0, 0.001, 0.0, 0.0, 0.0], 0.01, 4, 1, 1, 0),
+])
+def test_truncation_rule_hand_lines(line, frac, os_, q, h_max, h_expect):
+    assert H.truncated_half_support(np.asarray(line), frac, os_, q, h_max) == h_expect
+
+
 def test_truncation_monotone_and_clamped():
     wl = W.paper(n_planes=8, n_radial=1024)
     prev = None
