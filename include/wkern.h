@@ -44,6 +44,24 @@
  * - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls on
  *   one plan must not overlap in time: a plan serves one stream at a time.
  * - Generating calls are asynchronous with respect to the host.
+ * - A plan keeps a device status word.  The spline step, which reads every
+ *   radial-line value, flags a non-finite one (a NaN or infinite taper
+ *   sample or w gives one); wkern_sync_status reports and clears it.
+ *
+ * Environment (read by the host code at each call):
+ * - WKERN_TUNE_CACHE=<file>: the plan-time autotuner's results persist in
+ *   this text file, one line per device architecture, HIP runtime version,
+ *   library ABI version and geometry bucket; a plan whose key is present
+ *   takes the stored choice instead of timing the candidates.  Unset: every
+ *   plan times them.
+ * - WKERN_LOG=<level>: 0 silent (default), 1 a summary line per plan on
+ *   stderr, 2 also every error detail.
+ * - WKERN_FAULT=<site>[:<n>]: test hook.  The n-th (default first) event at
+ *   the site after the variable took this value fails once: "alloc" (a device
+ *   allocation of the library: OUT_OF_MEMORY), "launch" (a kernel launch of a
+ *   generating call: DEVICE), "capture" (the graph capture of wkern_generate:
+ *   DEVICE).  A failed call releases what it allocated and leaves the plan
+ *   usable.
  */
 #ifndef WKERN_H
 #define WKERN_H
@@ -55,7 +73,7 @@
 extern "C" {
 #endif
 
-#define WKERN_ABI_VERSION 2
+#define WKERN_ABI_VERSION 3
 
 typedef enum {
   WKERN_OK = 0,
@@ -63,14 +81,19 @@ typedef enum {
   WKERN_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
   WKERN_ERR_DEVICE = 3,        /* no usable device or a HIP runtime error */
   WKERN_ERR_UNSUPPORTED = 4,   /* valid request outside what the library implements */
-  WKERN_ERR_ABI_MISMATCH = 5   /* desc->abi_version != WKERN_ABI_VERSION */
+  WKERN_ERR_ABI_MISMATCH = 5,  /* desc->abi_version != WKERN_ABI_VERSION */
+  WKERN_ERR_NONFINITE = 6      /* a radial line held a non-finite value (wkern_sync_status) */
 } wkern_status;
 
 /* Arithmetic of the Hankel contraction (step 2).  The phase is always formed
  * in FP64.  FP32: M and s rounded to FP32, FP32 matrix-core products.
- * BF16X6: M and s each split into three BF16 terms (x ~ x0 + x1 + x2) and
- * combined with six products (02, 11, 20, 01, 10, 00).  Both accumulate in
- * FP32 over K-chunks of at most 256 radial nodes and combine chunks in FP64. */
+ * BF16X6: M and s rounded to FP32, each FP32 value split exactly into three
+ * BF16 terms (x = x0 + x1 + x2) and the terms combined with six BF16
+ * matrix-core products (02, 11, 20, 01, 10, 00); the split happens in
+ * registers after the operands are staged.  (The BF16-term variants, which
+ * wkern_set_variant can select, stage terms split from M's FP64 value and
+ * from the FP32 screen value.)  Both paths accumulate in FP32 over sub-chunks
+ * of 128 radial nodes and add the sub-chunk sums in FP64. */
 typedef enum { WKERN_PREC_FP32 = 0, WKERN_PREC_BF16X6 = 1 } wkern_precision;
 
 /* Interpolation of the radial line (section 4.3.2). */
@@ -266,8 +289,9 @@ wkern_status wkern_stage_times(wkern_plan_t plan, double* ms, int32_t* calls);
 
 /* Tuning state of a plan.  variant: the Hankel-contraction kernel variant
  * the plan-time autotuner chose (it times every candidate on the plan's own
- * tile lists); n_variants: number of candidates; variant_ms: host float
- * [n_variants], the measured time of each (may be NULL); chunks: number of
+ * tile lists, or takes the tuning cache's entry); n_variants: number of
+ * variants; variant_ms: host float [n_variants], the measured time of each
+ * (-1 for a variant that was not a candidate; may be NULL); chunks: number of
  * pipeline chunks (the resample of one chunk of planes overlaps the screen,
  * contraction and spline of the next).  Any output pointer may be NULL.
  * Errors: INVALID_ARG. */
@@ -280,7 +304,10 @@ wkern_status wkern_set_graph(wkern_plan_t plan, int32_t enable);
 
 /* Override the autotuner's choice of contraction variant (0 <= variant <
  * n_variants).  All variants compute the same sums in the same order per
- * output element.  Errors: INVALID_ARG. */
+ * output element.  The autotuner's candidates are the variants that stage
+ * FP32 operands; selecting a split-BF16 variant that stages BF16 terms
+ * builds those terms (M's and a screen buffer) on its first selection
+ * (synchronous then).  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant);
 
 /* Re-split the batch into `chunks` pipeline chunks of about equal cache
@@ -288,6 +315,14 @@ wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant);
  * other on the caller's stream).  Synchronous: waits for the plan's device
  * first.  Errors: INVALID_ARG (chunks < 1), DEVICE, OUT_OF_MEMORY. */
 wkern_status wkern_set_chunks(wkern_plan_t plan, int32_t chunks);
+
+/* Device status word of the plan: waits for `stream`, reads the word, and
+ * clears it.  WKERN_OK: no flag since the last read.  WKERN_ERR_NONFINITE: a
+ * generating call since then produced a non-finite radial-line value; the
+ * detail (wkern_last_error) names the first affected plane in caller order,
+ * and the affected planes' caches are unspecified.  Not allowed while
+ * `stream` is being captured (INVALID_ARG).  Errors: INVALID_ARG, DEVICE. */
+wkern_status wkern_sync_status(wkern_plan_t plan, void* stream);
 
 /* Release the plan and everything it owns.  Synchronises the plan's device
  * first.  NULL is accepted and ignored. */
@@ -314,7 +349,7 @@ const char* wkern_last_error(void);
 typedef struct wkern_fft2d_s* wkern_fft2d_t;
 
 /* workspace_mode 0: one N for all planes, the power of two at or above
- * max_support (the setting the paper's imager used, sections 5 and 6.3);
+ * max_support (the setting the paper's imager used, sections 5 and 6.4);
  * 1: per plane, the power of two at or above S_p.  workspace_bytes: device
  * memory for batched transforms (<= 0: 2 GiB); planes are transformed in
  * batches that fit it.  Uses d's geometry, supports and device; precision

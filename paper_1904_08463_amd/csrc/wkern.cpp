@@ -7,11 +7,16 @@
 
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -32,6 +37,7 @@ wkern_status fail(wkern_status s, const char* fmt, ...) {
   vsnprintf(buf, sizeof(buf), fmt, ap);
   va_end(ap);
   g_last_error = buf;
+  if (log_level() >= 2) fprintf(stderr, "wkern: error %d: %s\n", (int)s, buf);
   return s;
 }
 
@@ -48,7 +54,26 @@ wkern_status hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+// A kernel launch (through a launch_* helper); subject to WKERN_FAULT=launch.
+#define WK_LAUNCH(call, what)                                                      \
+  do {                                                                             \
+    if (fault_hit("launch"))                                                       \
+      return fail(WKERN_ERR_DEVICE, "%s: injected launch failure (WKERN_FAULT)", what); \
+    WK_HIP(call, what);                                                            \
+  } while (0)
+
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// The integer a C caller stored in an enum-typed field or argument.  C
+// allows any int there, but C++ may not load a value outside the
+// enumeration's range as the enum type, so the bits are read as an integer.
+template <class E>
+int32_t enum_bits(const E& e) {
+  static_assert(sizeof(E) == sizeof(int32_t), "enum fields are 32-bit in this ABI");
+  int32_t v;
+  std::memcpy(&v, &e, sizeof v);
+  return v;
+}
 
 // Validation shared by wkern_layout_desc and wkern_plan.
 wkern_status validate(const wkern_desc* d) {
@@ -80,10 +105,11 @@ wkern_status validate(const wkern_desc* d) {
   if (nrho_max > kMaxRho)
     return fail(WKERN_ERR_INVALID_ARG, "radial line of %lld nodes exceeds %d",
                 (long long)nrho_max, kMaxRho);
-  if (d->precision != WKERN_PREC_FP32 && d->precision != WKERN_PREC_BF16X6)
-    return fail(WKERN_ERR_INVALID_ARG, "unknown precision %d", (int)d->precision);
-  if (d->interp != WKERN_INTERP_LINEAR && d->interp != WKERN_INTERP_CUBIC)
-    return fail(WKERN_ERR_INVALID_ARG, "unknown interp %d", (int)d->interp);
+  const int32_t prec = enum_bits(d->precision), interp = enum_bits(d->interp);
+  if (prec != WKERN_PREC_FP32 && prec != WKERN_PREC_BF16X6)
+    return fail(WKERN_ERR_INVALID_ARG, "unknown precision %d", prec);
+  if (interp != WKERN_INTERP_LINEAR && interp != WKERN_INTERP_CUBIC)
+    return fail(WKERN_ERR_INVALID_ARG, "unknown interp %d", interp);
   for (int p = 0; p < d->n_planes; ++p) {
     const int s = d->support[p];
     if (s < 1 || (s % 2) == 0 || s > d->max_support)
@@ -138,6 +164,32 @@ struct DeviceGuard {
 
 void wkern::set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
 
+bool wkern::fault_hit(const char* site) {
+  static std::mutex mu;
+  static std::string armed;  // the WKERN_FAULT value the counter belongs to
+  static int count = 0;
+  const char* env = std::getenv("WKERN_FAULT");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!env || !*env) {
+    armed.clear();
+    return false;
+  }
+  if (armed != env) {
+    armed = env;
+    count = 0;
+  }
+  const char* colon = std::strchr(env, ':');
+  const size_t len = colon ? (size_t)(colon - env) : std::strlen(env);
+  if (len != std::strlen(site) || std::strncmp(env, site, len) != 0) return false;
+  const int nth = colon ? std::atoi(colon + 1) : 1;
+  return ++count == nth;
+}
+
+int wkern::log_level() {
+  const char* env = std::getenv("WKERN_LOG");
+  return env ? std::atoi(env) : 0;
+}
+
 // One profiled launch: stage index and the events around it.
 struct StageRecord {
   int stage;
@@ -168,6 +220,7 @@ struct wkern_plan_s {
   std::vector<int> chunkT[kNumVariants];  // [C + 1] tile boundaries
   int variant = kWave32x64;
   float variantMs[kNumVariants] = {};
+  bool tunedFromCache = false;
   // internal streams (default priority): sCompute is the capture stream of
   // the generation graph, sStore runs the resamples of a chunked pipeline
   hipStream_t sCompute = nullptr, sStore = nullptr;
@@ -223,6 +276,10 @@ struct wkern_plan_s {
   wkern_status alloc(T** ptr, size_t count, const char* what) {
     void* raw = nullptr;
     const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (fault_hit("alloc")) {
+      *ptr = nullptr;
+      return fail(WKERN_ERR_OUT_OF_MEMORY, "%s: injected allocation failure (WKERN_FAULT)", what);
+    }
     hipError_t e = hipMalloc(&raw, bytes);
     if (e != hipSuccess) {
       *ptr = nullptr;
@@ -335,13 +392,14 @@ extern "C" {
 int32_t wkern_abi_version(void) { return WKERN_ABI_VERSION; }
 
 const char* wkern_strerror(wkern_status s) {
-  switch (s) {
+  switch (enum_bits(s)) {
     case WKERN_OK: return "success";
     case WKERN_ERR_INVALID_ARG: return "invalid argument";
     case WKERN_ERR_OUT_OF_MEMORY: return "out of memory";
     case WKERN_ERR_DEVICE: return "device or HIP runtime error";
     case WKERN_ERR_UNSUPPORTED: return "unsupported";
     case WKERN_ERR_ABI_MISMATCH: return "ABI version mismatch";
+    case WKERN_ERR_NONFINITE: return "non-finite value in the generated kernels";
   }
   return "unknown status";
 }
@@ -428,6 +486,104 @@ static wkern_status build_chunks(wkern_plan_s* pl, int want) {
   pl->evChunk.assign(pl->nChunks, nullptr);
   for (auto& e : pl->evChunk)
     WK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+  return WKERN_OK;
+}
+
+// Persistent autotuner results.  WKERN_TUNE_CACHE names a text file with
+// one line per tuned geometry, "<key> <variant> <ms of each variant>"; the
+// key holds the device architecture, the HIP runtime version, the ABI
+// version and variant count of this library, the precision and a bucket of
+// the plan's geometry (padded Nr, K-chunk, computed planes and summed line
+// lengths rounded up to powers of two, padded rows of M), so a new ROCm or
+// library version never reuses an entry.  Unset: nothing is read or written.
+static std::string tune_key(const wkern_plan_s* pl, int device) {
+  const char* path = std::getenv("WKERN_TUNE_CACHE");
+  if (!path || !*path) return std::string();
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return std::string();
+  int rt = 0;
+  if (hipRuntimeGetVersion(&rt) != hipSuccess) return std::string();
+  const DevPlan& g = pl->dp;
+  int64_t sumRho = 0;
+  for (int32_t n : pl->nrhoSorted) sumRho += n;
+  auto pow2 = [](int64_t x) {
+    int64_t v = 1;
+    while (v < x) v <<= 1;
+    return (long long)v;
+  };
+  std::string arch(prop.gcnArchName);
+  for (char& c : arch)
+    if (c == ' ') c = '_';
+  char buf[384];
+  snprintf(buf, sizeof(buf), "%s|hip%d|abi%d|nv%d|prec%d|nr%d|kc%d|pc%lld|rows%d|rho%lld",
+           arch.c_str(), rt, WKERN_ABI_VERSION, (int)kNumVariants, g.precision, g.NrPad,
+           g.kchunk, pow2(g.P), g.rowsPad, pow2(sumRho));
+  return std::string(buf);
+}
+
+static std::mutex g_tune_mu;
+
+// Last entry of the cache file for `key` whose variant this precision
+// supports; false if there is none (or no readable file).
+static bool tune_lookup(const std::string& key, int precision, int* variant, float* ms) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  std::ifstream in(std::getenv("WKERN_TUNE_CACHE"));
+  if (!in) return false;
+  bool found = false;
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string k;
+    int v = -1;
+    if (!(ls >> k >> v) || k != key || v < 0 || v >= kNumVariants ||
+        !variant_supported(precision, v))
+      continue;
+    float t[kNumVariants];
+    int n = 0;
+    while (n < kNumVariants && (ls >> t[n])) ++n;
+    if (n != kNumVariants) continue;
+    *variant = v;
+    std::copy(t, t + kNumVariants, ms);
+    found = true;
+  }
+  return found;
+}
+
+static void tune_store(const std::string& key, int variant, const float* ms) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  std::ostringstream os;
+  os.precision(9);  // a float survives the text round trip exactly
+  os << key << ' ' << variant;
+  for (int v = 0; v < kNumVariants; ++v) os << ' ' << ms[v];
+  os << '\n';
+  FILE* f = std::fopen(std::getenv("WKERN_TUNE_CACHE"), "a");
+  if (!f) return;  // an unwritable cache only costs the next plan a re-tune
+  const std::string text = os.str();
+  std::fwrite(text.data(), 1, text.size(), f);
+  std::fclose(f);
+}
+
+// The BF16 terms of M and the BF16-term screen buffer, for the split
+// variants that stage them (built on the first selection of such a variant).
+static wkern_status ensure_split_terms(wkern_plan_s* pl) {
+  DevPlan& g = pl->dp;
+  if (g.Msplit) return WKERN_OK;
+  const size_t mElems = (size_t)g.rowsPad * g.NrPad;
+  const size_t bElems = (size_t)g.colsPad * g.NrPad;
+  wkern_status s;
+  if ((s = pl->alloc(&g.Msplit, mElems * 3, "Msplit")) != WKERN_OK) return s;
+  if ((s = pl->alloc(&g.Bsplit, bElems * 3, "screen buffer")) != WKERN_OK) {
+    pl->release(g.Msplit);
+    return s;
+  }
+  hipError_t e = hipMemset(g.Bsplit, 0, bElems * 3 * sizeof(uint16_t));
+  if (e == hipSuccess) e = launch_hankel_matrix(g, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    pl->release(g.Msplit);
+    pl->release(g.Bsplit);
+    return hip_fail(e, "BF16 terms of the HT matrix");
+  }
   return WKERN_OK;
 }
 
@@ -561,20 +717,21 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
 
   const size_t mElems = (size_t)g.rowsPad * g.NrPad;
   if ((s = pl->alloc(&g.M32, mElems, "M32")) != WKERN_OK) return s;
-  if ((s = pl->alloc(&g.Msplit, mElems * 3, "Msplit")) != WKERN_OK) return s;
-  const size_t bElems = (size_t)g.colsPad * g.NrPad;
   // the FP32 screen serves the FP32 path and the split path's FP32-operand
-  // variants; the BF16 terms only the other split variants
+  // variants; the BF16 terms of M and of the screen, which only the other
+  // split variants read, are built when such a variant is selected
+  const size_t bElems = (size_t)g.colsPad * g.NrPad;
   if ((s = pl->alloc(&g.B32, bElems, "screen buffer")) != WKERN_OK) return s;
   WK_HIP(hipMemset(g.B32, 0, bElems * sizeof(float)), "hipMemset");
-  if (g.precision == 1) {
-    if ((s = pl->alloc(&g.Bsplit, bElems * 3, "screen buffer")) != WKERN_OK) return s;
-    WK_HIP(hipMemset(g.Bsplit, 0, bElems * 3 * sizeof(uint16_t)), "hipMemset");
-  }
   if ((s = pl->alloc(&g.part, (size_t)g.nkc * g.lineTotal * 2, "partial sums")) != WKERN_OK)
     return s;
   if ((s = pl->alloc(&g.coef, (size_t)g.lineTotal * 2, "spline coefficients")) != WKERN_OK)
     return s;
+  if ((s = pl->alloc(&g.status, 2, "status word")) != WKERN_OK) return s;
+  {
+    const int32_t clear[2] = {0, INT32_MAX};
+    WK_HIP(hipMemcpy(g.status, clear, sizeof(clear), hipMemcpyHostToDevice), "status word");
+  }
 
   WK_HIP(prepare_kernels(g), "kernel attributes");
   WK_HIP(prepare_resample_kernels(g), "kernel attributes");
@@ -591,42 +748,22 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
   WK_HIP(hipEventCreateWithFlags(&pl->evFork, hipEventDisableTiming), "hipEventCreate");
   WK_HIP(hipEventCreateWithFlags(&pl->evJoinStore, hipEventDisableTiming), "hipEventCreate");
 
-  // Autotune: time every contraction variant on this plan's own tile lists
-  // (timing does not depend on the screen values), add the time of the
-  // screen kind it reads, and keep the fastest.
-  {
+  // Autotune: time every candidate contraction variant on this plan's own
+  // tile lists (timing does not depend on the screen values) and keep the
+  // fastest, unless the tuning cache already holds this geometry.  The
+  // candidates are the variants that read FP32 operands (every screen is
+  // then the same FP32 kernel); the BF16-term variants stay selectable
+  // through wkern_set_variant.
+  const std::string key = tune_key(pl, d->device);
+  if (!key.empty() && tune_lookup(key, g.precision, &pl->variant, pl->variantMs)) {
+    pl->tunedFromCache = true;
+  } else {
     hipEvent_t a, b;
     WK_HIP(hipEventCreate(&a), "hipEventCreate");
     WK_HIP(hipEventCreate(&b), "hipEventCreate");
-    // screen kernels on a constant taper and w = 0 (the values do not matter)
-    float screenMs[2] = {0.f, 0.f};
-    {
-      float* tau = nullptr;
-      double* w0 = nullptr;
-      if ((s = pl->alloc(&tau, (size_t)g.Nr, "autotune input")) != WKERN_OK) return s;
-      if ((s = pl->alloc(&w0, (size_t)P, "autotune input")) != WKERN_OK) return s;
-      WK_HIP(hipMemset(tau, 0, (size_t)g.Nr * sizeof(float)), "hipMemset");
-      WK_HIP(hipMemset(w0, 0, (size_t)P * sizeof(double)), "hipMemset");
-      for (int kind = 0; kind < 2; ++kind) {
-        if (kind == 0 && g.precision == 0) continue;  // no BF16 terms in an FP32 plan
-        float bestK = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-          WK_HIP(hipEventRecord(a, pl->sCompute), "hipEventRecord");
-          WK_HIP(launch_screen(g, 0, g.P, tau, w0, kind == 1, pl->sCompute), "autotune screen");
-          WK_HIP(hipEventRecord(b, pl->sCompute), "hipEventRecord");
-          WK_HIP(hipEventSynchronize(b), "hipEventSynchronize");
-          float ms = 0.f;
-          WK_HIP(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
-          if (rep > 0) bestK = std::min(bestK, ms);
-        }
-        screenMs[kind] = bestK;
-      }
-      pl->release(tau);
-      pl->release(w0);
-    }
     float best = 1e30f;
     for (int v = 0; v < kNumVariants; ++v) {
-      if (!variant_supported(g.precision, v)) {
+      if (!variant_supported(g.precision, v) || !variant_fp32_screen(g.precision, v)) {
         pl->variantMs[v] = -1.f;
         continue;
       }
@@ -641,7 +778,6 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
         WK_HIP(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
         if (rep > 0) bestV = std::min(bestV, ms);
       }
-      bestV += screenMs[variant_fp32_screen(g.precision, v) ? 1 : 0];
       pl->variantMs[v] = bestV;
       if (bestV < best) {
         best = bestV;
@@ -650,7 +786,12 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    if (!key.empty()) tune_store(key, pl->variant, pl->variantMs);
   }
+  if (log_level() >= 1)
+    fprintf(stderr, "wkern: plan P=%d (computed %d) Nr=%d os=%d precision=%d variant=%d (%s)\n",
+            g.Pall, g.P, g.Nr, g.os, g.precision, pl->variant,
+            pl->tunedFromCache ? "tuning cache" : "timed");
   return WKERN_OK;
 }
 
@@ -708,12 +849,12 @@ static wkern_status enqueue_lines(wkern_plan_t plan, const float* taper, const d
   const DevPlan& g = plan->dp;
   if (plan->engine == WKERN_ENGINE_MATRIX) {
     const int v = plan->variant;
-    WK_HIP(launch_screen(g, 0, g.P, taper, w, variant_fp32_screen(g.precision, v), st),
+    WK_LAUNCH(launch_screen(g, 0, g.P, taper, w, variant_fp32_screen(g.precision, v), st),
            "screen launch");
-    WK_HIP(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
+    WK_LAUNCH(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
            "contraction launch");
   } else {
-    WK_HIP(launch_ps_lines(g, plan->ps, 0, g.P, taper, w, st), "projection-slice launch");
+    WK_LAUNCH(launch_ps_lines(g, plan->ps, 0, g.P, taper, w, st), "projection-slice launch");
   }
   return WKERN_OK;
 }
@@ -730,25 +871,25 @@ static wkern_status enqueue_chunk(wkern_plan_t plan, int c, const float* taper, 
   wkern_status s;
   if (plan->engine == WKERN_ENGINE_MATRIX) {
     if ((s = plan->record_begin(0, compute, &r)) != WKERN_OK) return s;
-    WK_HIP(launch_screen(g, j0, j1, taper, w, variant_fp32_screen(g.precision, v), compute),
+    WK_LAUNCH(launch_screen(g, j0, j1, taper, w, variant_fp32_screen(g.precision, v), compute),
            "screen launch");
     if ((s = record_end(r, compute)) != WKERN_OK) return s;
     if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;
-    WK_HIP(launch_contract(g, v, plan->d_tiles[v] + t0, t1 - t0, compute), "contraction launch");
+    WK_LAUNCH(launch_contract(g, v, plan->d_tiles[v] + t0, t1 - t0, compute), "contraction launch");
   } else {
     if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;
-    WK_HIP(launch_ps_lines(g, plan->ps, j0, j1, taper, w, compute), "projection-slice launch");
+    WK_LAUNCH(launch_ps_lines(g, plan->ps, j0, j1, taper, w, compute), "projection-slice launch");
   }
   if ((s = record_end(r, compute)) != WKERN_OK) return s;
   if ((s = plan->record_begin(2, compute, &r)) != WKERN_OK) return s;
-  WK_HIP(launch_spline(lines_view(plan), j0, j1, compute), "spline launch");
+  WK_LAUNCH(launch_spline(lines_view(plan), j0, j1, compute), "spline launch");
   if ((s = record_end(r, compute)) != WKERN_OK) return s;
   if (handoff) {
     WK_HIP(hipEventRecord(handoff, compute), "hipEventRecord");
     WK_HIP(hipStreamWaitEvent(store, handoff, 0), "hipStreamWaitEvent");
   }
   if ((s = plan->record_begin(3, store, &r)) != WKERN_OK) return s;
-  WK_HIP(launch_resample(g, plan->chunkU[c], plan->chunkU[c + 1], out, store),
+  WK_LAUNCH(launch_resample(g, plan->chunkU[c], plan->chunkU[c + 1], out, store),
          "resample launch");
   return record_end(r, store);
 }
@@ -780,6 +921,8 @@ static wkern_status capture_graph(wkern_plan_t plan, const float* taper, const d
   WK_HIP(hipStreamBeginCapture(plan->sCompute, hipStreamCaptureModeRelaxed),
          "hipStreamBeginCapture");
   wkern_status s = enqueue_all(plan, taper, w, out, plan->sCompute);
+  if (s == WKERN_OK && fault_hit("capture"))
+    s = fail(WKERN_ERR_DEVICE, "graph capture: injected failure (WKERN_FAULT)");
   hipError_t e = hipStreamEndCapture(plan->sCompute, &graph);
   if (s != WKERN_OK) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -880,7 +1023,7 @@ wkern_status wkern_generate_truncated(wkern_plan_t plan, const float* taper, con
   if ((s = ensure_trunc_scratch(plan)) != WKERN_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   if ((s = enqueue_lines(plan, taper, w, st)) != WKERN_OK) return s;
-  WK_HIP(launch_resample_truncated(lines_view(plan), plan->trunc, frac, support_out, offsets_out,
+  WK_LAUNCH(launch_resample_truncated(lines_view(plan), plan->trunc, frac, support_out, offsets_out,
                                    out, st),
          "truncated resample launch");
   return WKERN_OK;
@@ -898,8 +1041,8 @@ wkern_status wkern_prepare_lines(wkern_plan_t plan, const float* taper, const do
   if ((s = enqueue_lines(plan, taper, w, st)) != WKERN_OK) return s;
   const DevPlan view = lines_view(plan);
   int32_t* hT = frac > 0.0 ? plan->trunc.hTrunc : nullptr;
-  WK_HIP(launch_spline(view, 0, view.P, st, frac, hT), "spline launch");
-  WK_HIP(launch_supports(view, hT, hT ? plan->trunc.sortedPos : nullptr, support_out, st),
+  WK_LAUNCH(launch_spline(view, 0, view.P, st, frac, hT), "spline launch");
+  WK_LAUNCH(launch_supports(view, hT, hT ? plan->trunc.sortedPos : nullptr, support_out, st),
          "supports launch");
   return WKERN_OK;
 }
@@ -925,7 +1068,7 @@ wkern_status wkern_grid(wkern_plan_t plan, const double* u, const double* v, con
       (s = plan->alloc(&plan->gridChunks, (size_t)plan->dp.Pall + 1, "gridding table")) != WKERN_OK)
     return s;
   const double du = 1.0 / ((double)plan->desc.image_size * plan->desc.cellsize);
-  WK_HIP(launch_grid(lines_view(plan), plan->gridChunks, u, v, w, vis, n_records, order,
+  WK_LAUNCH(launch_grid(lines_view(plan), plan->gridChunks, u, v, w, vis, n_records, order,
                      plane_start, support, cache, cache_offsets, grid_size, du, grid,
                      (hipStream_t)stream),
          "gridding launch");
@@ -1030,6 +1173,12 @@ wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant) {
     return fail(WKERN_ERR_INVALID_ARG, "variant %d not in [0, %d)", variant, kNumVariants);
   if (!variant_supported(plan->dp.precision, variant))
     return fail(WKERN_ERR_INVALID_ARG, "variant %d is not available for this precision", variant);
+  DeviceGuard guard(plan->desc.device);
+  if (!variant_fp32_screen(plan->dp.precision, variant)) {
+    WK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    wkern_status s = ensure_split_terms(plan);
+    if (s != WKERN_OK) return s;
+  }
   plan->variant = variant;
   plan->graphValid = false;
   return WKERN_OK;
@@ -1057,7 +1206,7 @@ wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const 
   DeviceGuard guard(plan->desc.device);
   hipStream_t st = (hipStream_t)stream;
   if ((s = enqueue_lines(plan, taper, w, st)) != WKERN_OK) return s;
-  WK_HIP(launch_lines_out(lines_view(plan), lines, st), "lines launch");
+  WK_LAUNCH(launch_lines_out(lines_view(plan), lines, st), "lines launch");
   return WKERN_OK;
 }
 
@@ -1094,9 +1243,31 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
     }
     plan->gradReady = true;
   }
-  WK_HIP(launch_grad(g, plan->grad, taper, w, grad_out, grad_taper, grad_w, (hipStream_t)stream),
+  WK_LAUNCH(launch_grad(g, plan->grad, taper, w, grad_out, grad_taper, grad_w, (hipStream_t)stream),
          "gradient launch");
   return WKERN_OK;
+}
+
+wkern_status wkern_sync_status(wkern_plan_t plan, void* stream) {
+  clear_error();
+  if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
+  DeviceGuard guard(plan->desc.device);
+  hipStream_t st = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  WK_HIP(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(WKERN_ERR_INVALID_ARG, "stream is being captured; the status word needs a wait");
+  int32_t word[2] = {0, INT32_MAX};
+  WK_HIP(hipMemcpyAsync(word, plan->dp.status, sizeof(word), hipMemcpyDeviceToHost, st),
+         "status read");
+  WK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (word[0] == 0) return WKERN_OK;
+  const int32_t clear[2] = {0, INT32_MAX};
+  WK_HIP(hipMemcpy(plan->dp.status, clear, sizeof(clear), hipMemcpyHostToDevice), "status clear");
+  if (word[0] & kStatusNonFinite)
+    return fail(WKERN_ERR_NONFINITE,
+                "non-finite radial line value; first affected plane %d (caller order)", word[1]);
+  return fail(WKERN_ERR_DEVICE, "device status word 0x%x", (unsigned)word[0]);
 }
 
 wkern_status wkern_destroy(wkern_plan_t plan) {

@@ -11,6 +11,14 @@ namespace wkern {
 // Sets the calling thread's detail string returned by wkern_last_error().
 void set_last_error(const char* msg);
 
+// Host-side fault injection: WKERN_FAULT = "<site>[:<n>]" makes the n-th
+// (default first) event at that site after the variable was set fail once
+// ("alloc": a device allocation, "launch": a kernel launch, "capture": the
+// graph capture of wkern_generate).  Unset or empty: never.
+bool fault_hit(const char* site);
+// WKERN_LOG: 0 (default, silent), 1 plan summaries, 2 also every error.
+int log_level();
+
 // Radial K-chunk accumulated in FP32 inside the matrix cores before it is
 // added to an FP64 running sum.
 constexpr int kSubChunk = 128;
@@ -115,7 +123,13 @@ struct DevPlan {
   uint16_t* Bsplit;       // [colsPad][NrPad/8][3][8]
   double* part;           // [nkc][lineTotal][2]
   float4* coef;           // [lineTotal][2]
+  // device status word: [0] flag bits (kStatusNonFinite), [1] smallest
+  // caller index of a plane whose radial line held a non-finite value
+  int32_t* status;
 };
+
+// Bits of the device status word.
+constexpr int32_t kStatusNonFinite = 1;
 
 // Scratch of the adjoint (allocated on the first gradient call).
 struct GradScratch {

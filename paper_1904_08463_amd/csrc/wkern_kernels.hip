@@ -43,7 +43,8 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
 // Discrete HT matrix (section 4.3): M[k, i] = 2 pi J0(2 pi rho_k r_i) r_i dr,
 // midpoint nodes r_i = (i + 1/2) dr, rho_k = k drho.  FP64 with the device
 // j0; stored as FP32 and as three BF16 terms split from the FP64 value,
-// grouped by 8 radial nodes: Msplit[k][i/8][term][i%8].
+// grouped by 8 radial nodes: Msplit[k][i/8][term][i%8] (when Msplit is not
+// null).
 // --------------------------------------------------------------------------
 __global__ void k_hankel_matrix(int rowsPad, int NrPad, int Nr, int nrhoMax, double dr,
                                 double drho, float* __restrict__ M32,
@@ -58,6 +59,7 @@ __global__ void k_hankel_matrix(int rowsPad, int NrPad, int Nr, int nrhoMax, dou
     m = kTwoPi * j0(kTwoPi * rho * r) * r * dr;
   }
   M32[(size_t)k * NrPad + i] = (float)m;
+  if (!Msplit) return;  // the BF16 terms are built only for the variants that read them
   const uint16_t t0 = bf16_rne((float)m);
   double rem = m - (double)bf16_to_f(t0);
   const uint16_t t1 = bf16_rne((float)rem);
@@ -1297,7 +1299,9 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
                                                const double* __restrict__ cprime,
                                                const double* __restrict__ part,
                                                float4* __restrict__ coef, double frac2,
-                                               int qos, int32_t* __restrict__ hTrunc) {
+                                               int qos, int32_t* __restrict__ hTrunc,
+                                               const int32_t* __restrict__ perm,
+                                               int32_t* __restrict__ status) {
   extern __shared__ double2 smem[];
   // c'_k for k < 64; the recurrence reaches its FP64 fixed point by k = 15,
   // so c'_k = c'_63 for every k >= 63
@@ -1315,6 +1319,7 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
   // the K-chunk partial sums, added in chunk order, eight nodes per lane in
   // flight (loads past the line re-read its last node and are dropped)
   const double2* partL = (const double2*)part + off;
+  bool finite = true;
   for (int k0 = lane; k0 < n; k0 += 64 * 8) {
     double2 acc[8];
 #pragma unroll
@@ -1331,7 +1336,16 @@ __global__ __launch_bounds__(64) void k_spline(int j0, int nkc, int lineTotal, i
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (k0 + 64 * u < n) y[k0 + 64 * u] = acc[u];
+      if (k0 + 64 * u < n) {
+        y[k0 + 64 * u] = acc[u];
+        finite = finite && isfinite(acc[u].x) && isfinite(acc[u].y);
+      }
+  }
+  // a non-finite line value (from a non-finite taper sample or w) sets the
+  // plan's status word; the line's cache is then unspecified
+  if (__any(!finite) && lane == 0) {
+    atomicOr(&status[0], kStatusNonFinite);
+    atomicMin(&status[1], perm[j]);
   }
   __syncthreads();
 
@@ -2143,7 +2157,7 @@ hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s, double
     const size_t shm = (size_t)3 * nmax * sizeof(double2);
     hipLaunchKernelGGL(k_spline, dim3(jb - j0), dim3(64), shm, s, j0, p.nkc, p.lineTotal,
                        p.interp, p.nrhoSorted, p.lineOffSorted, p.cprime, p.part, p.coef,
-                       frac * frac, p.q * p.os, hTrunc);
+                       frac * frac, p.q * p.os, hTrunc, p.perm, p.status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     j0 = jb;

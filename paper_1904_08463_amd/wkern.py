@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwkern.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 PRECISION = {"fp32": 0, "bf16x6": 1}
 INTERP = {"linear": 0, "cubic": 1}
 STATUS = {
@@ -26,6 +26,7 @@ STATUS = {
     3: "WKERN_ERR_DEVICE",
     4: "WKERN_ERR_UNSUPPORTED",
     5: "WKERN_ERR_ABI_MISMATCH",
+    6: "WKERN_ERR_NONFINITE",
 }
 
 # every symbol include/wkern.h declares
@@ -33,7 +34,7 @@ EXPORTS = (
     "wkern_abi_version", "wkern_layout_desc", "wkern_plan", "wkern_layout",
     "wkern_generate", "wkern_generate_truncated", "wkern_generate_radial", "wkern_grad", "wkern_set_profiling",
     "wkern_stage_times", "wkern_plan_info", "wkern_set_variant",
-    "wkern_set_chunks", "wkern_set_graph", "wkern_set_engine", "wkern_destroy",
+    "wkern_set_chunks", "wkern_set_graph", "wkern_set_engine", "wkern_sync_status", "wkern_destroy",
     "wkern_strerror", "wkern_last_error",
     "wkern_fft2d_plan", "wkern_fft2d_generate", "wkern_fft2d_destroy",
     "wkern_wpartition_workspace", "wkern_wpartition",
@@ -110,6 +111,8 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_set_engine.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     lib.wkern_set_chunks.restype = ctypes.c_int
     lib.wkern_set_chunks.argtypes = [vp, ctypes.c_int32]
+    lib.wkern_sync_status.restype = ctypes.c_int
+    lib.wkern_sync_status.argtypes = [vp, vp]
     lib.wkern_destroy.restype = ctypes.c_int
     lib.wkern_destroy.argtypes = [vp]
     lib.wkern_strerror.restype = ctypes.c_char_p
@@ -385,6 +388,12 @@ class Plan:
         workspace per plane or fixed at the maximum support."""
         _check(load_library().wkern_set_engine(self._h, self.ENGINES[engine],
                                                self.PS_WORKSPACE[workspace]))
+
+    def sync_status(self, stream=None):
+        """Wait for the stream, then raise WkernError (WKERN_ERR_NONFINITE) if a
+        generating call since the last check produced a non-finite radial-line
+        value; clears the device status word."""
+        _check(load_library().wkern_sync_status(self._h, _stream_handle(stream)))
 
     def set_chunks(self, chunks: int):
         _check(load_library().wkern_set_chunks(self._h, int(chunks)))
