@@ -110,7 +110,10 @@ def test_nonfinite_taper_flags_every_path():
 # fault injection
 # ---------------------------------------------------------------------------
 def _free_bytes():
+    """Free device memory with torch's cached blocks returned to the device
+    (the library allocates with hipMalloc, outside torch's allocator)."""
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     return torch.cuda.mem_get_info()[0]
 
 
@@ -138,6 +141,7 @@ def test_injected_allocation_failure_leaks_nothing(env, nth):
         got = flat[plan.offsets[p]:plan.offsets[p + 1]].reshape(caches[j].shape)
         assert _rel(got, caches[j]) <= 1e-6
     plan.close()
+    del taper, w
     assert _free_bytes() == before
 
 
