@@ -408,6 +408,20 @@ wkern_status wkern_wpartition(const double* w, int64_t n_records, int32_t n_plan
                               size_t workspace_bytes, int32_t* order, int64_t* plane_start,
                               double* w_plane, void* stream);
 
+/* wkern_wpartition without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the keys, record indices and sort storage live in
+ * a static 64 MiB device array of the library, held on each device it runs on
+ * until the process ends; nothing is allocated.  Same arguments, results and
+ * errors as wkern_wpartition minus the workspace, on the current device;
+ * additionally INVALID_ARG for n_records above 2^20 (1048576), the most the
+ * array holds.  Every call on a device shares that device's array: calls
+ * that overlap in time on one device (other streams, other threads) race
+ * and must be serialised by the caller.  Asynchronous on `stream`. */
+wkern_status wkern_wpartition_noalloc(const double* w, int64_t n_records, int32_t n_planes,
+                                      int32_t absolute, int32_t stat, int32_t* order,
+                                      int64_t* plane_start, double* w_plane, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
+
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "wkern.h"
@@ -113,6 +115,84 @@ size_t workspace_total(int n, size_t tmp) {
   return align_up((size_t)n * 8) * 2 + align_up((size_t)n * 4) + align_up(tmp);
 }
 
+// Scratch of wkern_wpartition_noalloc: the keys, record indices and sort
+// storage of wkern_wpartition's workspace, in a device array that the
+// library holds for the life of the process (one copy per device, at its own
+// address on each).  Host code never uses the array's name as an address:
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int64_t kStaticMaxRecords = (int64_t)1 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+wkern_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return pfail(WKERN_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return pfail(WKERN_ERR_UNSUPPORTED, "device %d beyond the %d the static scratch covers", dev,
+                 kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return pfail(WKERN_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return WKERN_OK;
+}
+
+wkern_status check_partition_args(const double* w, int64_t n_records, int32_t n_planes,
+                                  int32_t absolute, int32_t stat, const int32_t* order,
+                                  const int64_t* plane_start, const double* w_plane) {
+  if (!w || !order || !plane_start || !w_plane) return pfail(WKERN_ERR_INVALID_ARG, "NULL argument");
+  if (n_planes < 1 || n_records < n_planes)
+    return pfail(WKERN_ERR_INVALID_ARG, "need n_records (%lld) >= n_planes (%d) >= 1",
+                 (long long)n_records, n_planes);
+  if (n_records > 0x7FFFFFFF)
+    return pfail(WKERN_ERR_UNSUPPORTED, "n_records %lld above 2^31 - 1", (long long)n_records);
+  if (absolute != 0 && absolute != 1) return pfail(WKERN_ERR_INVALID_ARG, "absolute must be 0 or 1");
+  if (stat != WKERN_WSTAT_MEAN && stat != WKERN_WSTAT_MEDIAN)
+    return pfail(WKERN_ERR_INVALID_ARG, "stat %d unknown", stat);
+  return WKERN_OK;
+}
+
+// The partition with its scratch at `base` (256-byte aligned, `bytes` long):
+// keys, sort, plane statistics, all on `s`.
+wkern_status partition_into(const double* w, int n, int32_t n_planes, int32_t absolute,
+                            int32_t stat, char* base, size_t bytes, int32_t* order,
+                            int64_t* plane_start, double* w_plane, hipStream_t s) {
+  size_t tmp = 0;
+  wkern_status st = sort_storage(n, s, &tmp);
+  if (st != WKERN_OK) return st;
+  const size_t need = workspace_total(n, tmp);
+  if (bytes < need) return pfail(WKERN_ERR_INVALID_ARG, "workspace %zu bytes < %zu", bytes, need);
+  if ((uintptr_t)base % kAlign)
+    return pfail(WKERN_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
+  uint64_t* keysIn = (uint64_t*)base;
+  uint64_t* keysOut = (uint64_t*)(base + align_up((size_t)n * 8));
+  int32_t* idxIn = (int32_t*)(base + 2 * align_up((size_t)n * 8));
+  void* sortTmp = base + 2 * align_up((size_t)n * 8) + align_up((size_t)n * 4);
+
+  const int grid = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+  hipLaunchKernelGGL(k_wkeys, dim3(grid), dim3(256), 0, s, w, n, absolute, keysIn, idxIn);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return pfail(WKERN_ERR_DEVICE, "key launch: %s", hipGetErrorString(e));
+  e = rocprim::radix_sort_pairs(sortTmp, tmp, keysIn, keysOut, idxIn, order, n, 0, 64, s);
+  if (e != hipSuccess) return pfail(WKERN_ERR_DEVICE, "radix sort: %s", hipGetErrorString(e));
+  hipLaunchKernelGGL(k_wplane_stats, dim3(n_planes), dim3(kStatThreads), 0, s, keysOut,
+                     (int64_t)n, n_planes, absolute, stat, plane_start, w_plane);
+  e = hipGetLastError();
+  if (e != hipSuccess) return pfail(WKERN_ERR_DEVICE, "plane statistics launch: %s", hipGetErrorString(e));
+  return WKERN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -135,43 +215,30 @@ wkern_status wkern_wpartition(const double* w, int64_t n_records, int32_t n_plan
                               size_t workspace_bytes, int32_t* order, int64_t* plane_start,
                               double* w_plane, void* stream) {
   wkern::set_last_error("");
-  if (!w || !workspace || !order || !plane_start || !w_plane)
-    return pfail(WKERN_ERR_INVALID_ARG, "NULL argument");
-  if (n_planes < 1 || n_records < n_planes)
-    return pfail(WKERN_ERR_INVALID_ARG, "need n_records (%lld) >= n_planes (%d) >= 1",
-                 (long long)n_records, n_planes);
-  if (n_records > 0x7FFFFFFF)
-    return pfail(WKERN_ERR_UNSUPPORTED, "n_records %lld above 2^31 - 1", (long long)n_records);
-  if (absolute != 0 && absolute != 1) return pfail(WKERN_ERR_INVALID_ARG, "absolute must be 0 or 1");
-  if (stat != WKERN_WSTAT_MEAN && stat != WKERN_WSTAT_MEDIAN)
-    return pfail(WKERN_ERR_INVALID_ARG, "stat %d unknown", stat);
-  const int n = (int)n_records;
-  hipStream_t s = (hipStream_t)stream;
-  size_t tmp = 0;
-  wkern_status st = sort_storage(n, s, &tmp);
+  wkern_status st =
+      check_partition_args(w, n_records, n_planes, absolute, stat, order, plane_start, w_plane);
   if (st != WKERN_OK) return st;
-  const size_t need = workspace_total(n, tmp);
-  if (workspace_bytes < need)
-    return pfail(WKERN_ERR_INVALID_ARG, "workspace %zu bytes < %zu", workspace_bytes, need);
-  char* base = (char*)workspace;
-  if ((uintptr_t)base % kAlign)
-    return pfail(WKERN_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
-  uint64_t* keysIn = (uint64_t*)base;
-  uint64_t* keysOut = (uint64_t*)(base + align_up((size_t)n * 8));
-  int32_t* idxIn = (int32_t*)(base + 2 * align_up((size_t)n * 8));
-  void* sortTmp = base + 2 * align_up((size_t)n * 8) + align_up((size_t)n * 4);
+  if (!workspace) return pfail(WKERN_ERR_INVALID_ARG, "NULL argument");
+  return partition_into(w, (int)n_records, n_planes, absolute, stat, (char*)workspace,
+                        workspace_bytes, order, plane_start, w_plane, (hipStream_t)stream);
+}
 
-  const int grid = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
-  hipLaunchKernelGGL(k_wkeys, dim3(grid), dim3(256), 0, s, w, n, absolute, keysIn, idxIn);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return pfail(WKERN_ERR_DEVICE, "key launch: %s", hipGetErrorString(e));
-  e = rocprim::radix_sort_pairs(sortTmp, tmp, keysIn, keysOut, idxIn, order, n, 0, 64, s);
-  if (e != hipSuccess) return pfail(WKERN_ERR_DEVICE, "radix sort: %s", hipGetErrorString(e));
-  hipLaunchKernelGGL(k_wplane_stats, dim3(n_planes), dim3(kStatThreads), 0, s, keysOut,
-                     (int64_t)n, n_planes, absolute, stat, plane_start, w_plane);
-  e = hipGetLastError();
-  if (e != hipSuccess) return pfail(WKERN_ERR_DEVICE, "plane statistics launch: %s", hipGetErrorString(e));
-  return WKERN_OK;
+wkern_status wkern_wpartition_noalloc(const double* w, int64_t n_records, int32_t n_planes,
+                                      int32_t absolute, int32_t stat, int32_t* order,
+                                      int64_t* plane_start, double* w_plane, void* stream) {
+  wkern::set_last_error("");
+  wkern_status st =
+      check_partition_args(w, n_records, n_planes, absolute, stat, order, plane_start, w_plane);
+  if (st != WKERN_OK) return st;
+  if (n_records > kStaticMaxRecords)
+    return pfail(WKERN_ERR_INVALID_ARG,
+                 "n_records %lld above %lld, the most the static scratch holds; use "
+                 "wkern_wpartition with a workspace",
+                 (long long)n_records, (long long)kStaticMaxRecords);
+  void* base = nullptr;
+  if ((st = static_scratch(&base)) != WKERN_OK) return st;
+  return partition_into(w, (int)n_records, n_planes, absolute, stat, (char*)base,
+                        kStaticScratchBytes, order, plane_start, w_plane, (hipStream_t)stream);
 }
 
 }  // extern "C"

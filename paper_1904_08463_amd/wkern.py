@@ -37,7 +37,7 @@ EXPORTS = (
     "wkern_set_chunks", "wkern_set_graph", "wkern_set_engine", "wkern_sync_status", "wkern_destroy",
     "wkern_strerror", "wkern_last_error",
     "wkern_fft2d_plan", "wkern_fft2d_generate", "wkern_fft2d_destroy",
-    "wkern_wpartition_workspace", "wkern_wpartition",
+    "wkern_wpartition_workspace", "wkern_wpartition", "wkern_wpartition_noalloc",
     "wkern_prepare_lines", "wkern_grid",
 )
 
@@ -135,6 +135,9 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_wpartition.restype = ctypes.c_int
     lib.wkern_wpartition.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, vp, ctypes.c_size_t, vp, vp, vp, vp]
+    lib.wkern_wpartition_noalloc.restype = ctypes.c_int
+    lib.wkern_wpartition_noalloc.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, vp, vp, vp, vp]
     if lib.wkern_abi_version() != ABI_VERSION:
         raise WkernError(5, f"library ABI {lib.wkern_abi_version()}, binding {ABI_VERSION}")
     _lib = lib
@@ -511,3 +514,34 @@ def wpartition(w, n_planes: int, absolute: bool = True, stat: str = "mean", work
         _ptr(w), n, int(n_planes), 1 if absolute else 0, WSTAT[stat], _ptr(workspace),
         workspace.numel(), _ptr(order), _ptr(start), _ptr(w_plane), _stream_handle(stream)))
     return order, start, w_plane
+
+
+NOALLOC_MAX_RECORDS = 1 << 20
+
+
+def wpartition_noalloc(w, n_planes: int, absolute: bool = True, stat: str = "mean", order=None,
+                       plane_start=None, w_plane=None, stream=None):
+    """wpartition without a workspace (the library's static device scratch;
+    at most 2^20 records; calls on one device must not overlap).  Outputs
+    may be passed in (order int32 [n], plane_start int64 [M + 1], w_plane
+    float64 [M]); any that is None is allocated here with torch."""
+    import torch
+    if w.dtype != torch.float64 or not w.is_cuda or w.dim() != 1:
+        raise ValueError("w must be a 1-D float64 device tensor")
+    w = w.contiguous()
+    n = w.numel()
+    dev = w.device
+    if order is None:
+        order = torch.empty(n, dtype=torch.int32, device=dev)
+    if plane_start is None:
+        plane_start = torch.empty(n_planes + 1, dtype=torch.int64, device=dev)
+    if w_plane is None:
+        w_plane = torch.empty(n_planes, dtype=torch.float64, device=dev)
+    _require(order, torch.int32, "order", numel=n, device=dev.index)
+    _require(plane_start, torch.int64, "plane_start", numel=n_planes + 1, device=dev.index)
+    _require(w_plane, torch.float64, "w_plane", numel=n_planes, device=dev.index)
+    with torch.cuda.device(dev):
+        _check(load_library().wkern_wpartition_noalloc(
+            _ptr(w), n, int(n_planes), 1 if absolute else 0, WSTAT[stat], _ptr(order),
+            _ptr(plane_start), _ptr(w_plane), _stream_handle(stream)))
+    return order, plane_start, w_plane
