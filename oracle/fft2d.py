@@ -31,7 +31,7 @@ TWO_PI = 2.0 * math.pi
 
 
 def next_pow2(n: int) -> int:
-    """Smallest power of two >= n (section 4.2 and section 6.3: the workspace is
+    """Smallest power of two >= n (section 4.2 and section 6.4: the workspace is
     the power of two at or above the full kernel size 2 support + 1)."""
     p = 1
     while p < n:

@@ -16,7 +16,7 @@ interpolation and the transform's sign and scale):
 
 PS1 The workspace of a plane is the power of two at or above its full width
     S_p (section 4.2, workspace undersampling), or at or above the maximum
-    support for every plane (the fixed setting of sections 5 and 6.3), and
+    support for every plane (the fixed setting of sections 5 and 6.4), and
     at least 2 (a centred workspace needs an even width); it is doubled
     until the padded transform reaches the line's last node,
     q os N_ws / 2 >= nrho = q os h + 4.
