@@ -1,7 +1,20 @@
 """Gradients of the HIP adjoint (through the C ABI and torch.autograd) against
 the FP64 oracle's gradient, central finite differences of the oracle, and a
-dot-product test of the device adjoint.  Gate: max |g - g_ref| / max |g_ref|
-<= 1e-4 for dL/dtaper and dL/dw."""
+dot-product test of the device adjoint.
+
+Gates (error = max |g - g_ref| / max |g_ref| unless stated):
+- the device adjoint fed the oracle's dL/dcache: 1e-4 for dL/dtaper and
+  dL/dw, against the oracle's gradient and against central differences of the
+  oracle (every w-coordinate, 32 taper coordinates, 16 taper directions,
+  tests/golden/grad_fd.json); a directional derivative within 1e-4 of |FD|;
+- end to end (device forward, torch loss, device backward): dL/dtaper 1e-4;
+  dL/dw W_GATE (2e-3 split-BF16, 1e-2 FP32), since the window loss sees only
+  the kernel tail (about 5e-6 of the peak) and dL/dw inherits the forward's
+  absolute error there; a directional derivative within 1e-3 of |FD|.
+"""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -105,13 +118,66 @@ def test_autograd_end_to_end(grad_ref):
         print(f"w[{p}]: FD {fd:.6e}, oracle adjoint {gw_ref[p]:.6e}, device {gw[p]:.6e}", flush=True)
         # central differences at h = 1e-4 carry an O(h^2) truncation error of ~2e-6
         assert abs(gw_ref[p] - fd) <= 1e-5 * np.max(np.abs(gw_ref))
+        assert abs(gw[p] - fd) <= W_GATE["fp32"] * np.max(np.abs(gw_ref))
     rng = np.random.default_rng(W.SEED)
     v = rng.normal(size=wl.n_radial)
     v /= np.linalg.norm(v)
     fd = (_oracle_loss(wl, tau + h * v, wl.w, 31)[0] - _oracle_loss(wl, tau - h * v, wl.w, 31)[0]) / (2 * h)
     dd = float(np.dot(gt, v))
     print(f"directional FD {fd:.6e}, device {dd:.6e}, oracle {float(np.dot(gt_ref, v)):.6e}", flush=True)
-    assert abs(dd - fd) <= GATE * np.linalg.norm(gt_ref)
+    assert abs(dd - fd) <= 1e-3 * abs(fd)
+
+
+FD_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grad_fd.json")
+
+
+def _fd_golden():
+    with open(FD_FILE) as f:
+        return json.load(f)
+
+
+def test_device_gradient_against_finite_differences(grad_ref):
+    """Every w-coordinate, 32 taper coordinates (the last 8 next to r_max) and
+    16 seeded taper directions, against central differences (h = 1e-4) of the
+    oracle's loss: the device adjoint alone (fed the oracle's dL/dcache) and
+    the device gradient end to end, per plane."""
+    from paper_1904_08463_amd import Plan
+    wl, tau, _, g_cache, gt_ref, gw_ref = grad_ref
+    fd = _fd_golden()
+    w_fd = np.asarray(fd["w_fd"])
+    coords = np.asarray(fd["tau_coords"])
+    assert np.array_equal(coords, W.fd_taper_coords(wl.n_radial))
+    t_fd, d_fd = np.asarray(fd["tau_fd"]), np.asarray(fd["direction_fd"])
+    dirs = W.fd_directions(wl.n_radial)
+    gmax_w, gmax_t = np.max(np.abs(gw_ref)), np.max(np.abs(gt_ref))
+    # the oracle's own adjoint against its differences (the reference is sound)
+    assert np.max(np.abs(gw_ref - w_fd)) <= 1e-5 * gmax_w
+    assert np.max(np.abs(gt_ref[coords] - t_fd)) <= 1e-6 * gmax_t
+
+    def report(tag, gt, gw, w_gate, d_gate):
+        ew = np.abs(gw - w_fd) / gmax_w
+        et = np.abs(gt[coords] - t_fd) / gmax_t
+        ed = np.abs(dirs @ gt - d_fd) / np.abs(d_fd)
+        worst = np.argsort(ew)[::-1][:5]
+        print(f"{tag}: dL/dw vs FD max {ew.max():.2e} (median {np.median(ew):.2e}; worst planes "
+              f"{', '.join(f'{p}:{ew[p]:.1e}' for p in worst)}); dL/dtaper at 32 nodes "
+              f"{et.max():.2e} (last 8 {et[-8:].max():.2e}); 16 directions, relative to |FD| "
+              f"{ed.max():.2e}", flush=True)
+        assert ew.max() <= w_gate
+        assert et.max() <= GATE
+        assert ed.max() <= d_gate
+
+    plan = Plan.from_workload(wl)
+    flat = np.concatenate([c.reshape(-1) for c in g_cache]).astype(np.complex64)
+    gt, gw = plan.grad(torch.from_numpy(wl.taper).cuda(), torch.from_numpy(wl.w).cuda(),
+                       torch.from_numpy(flat).cuda())
+    plan.close()
+    report("adjoint alone", gt.cpu().numpy().astype(np.float64), gw.cpu().numpy(), GATE, 1e-4)
+    for precision in ("bf16x6", "fp32"):
+        plan = Plan.from_workload(wl, precision=precision)
+        _, gt, gw = _device_loss_grad(wl, plan, 31)
+        plan.close()
+        report(f"end to end {precision}", gt, gw, W_GATE[precision], 1e-3)
 
 
 @pytest.mark.parametrize("interp,q", [("cubic", 1), ("linear", 1), ("cubic", 2)])

@@ -225,6 +225,20 @@ def grad(n_planes: int = 256, n_radial: int = 2048, noise: float = 1e-3,
         notes="free taper samples (PSWF + noise), S = 127")
 
 
+def fd_directions(n: int, count: int = 16, seed: int = SEED) -> np.ndarray:
+    """Seeded unit directions [count, n] for directional finite differences."""
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=(count, n))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def fd_taper_coords(n: int, count: int = 32, tail: int = 8) -> np.ndarray:
+    """Taper coordinates for finite differences: count - tail spread over the
+    radial nodes and the last `tail` nodes (next to r_max)."""
+    spread = np.rint(np.linspace(0, n - tail - 1, count - tail)).astype(np.int64)
+    return np.concatenate([spread, np.arange(n - tail, n)])
+
+
 def random_small(seed: int, n_planes: int = 5, n_radial: int = 96, os_: int = 3,
                  max_support: int = 21, precision: str = "fp32", interp: str = "cubic",
                  radial_refine: int = 1) -> Workload:
