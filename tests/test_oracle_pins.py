@@ -599,3 +599,27 @@ def test_adjoint_matches_torch_autodiff(interp):
     g_tau, g_w = A.grad(image_size, cell, nr, os_, tau, w, support, g_caches, q, interp)
     assert np.max(np.abs(g_tau - t_tau.grad.numpy())) <= 1e-10 * np.max(np.abs(g_tau))
     assert np.max(np.abs(g_w - t_w.grad.numpy())) <= 1e-10 * np.max(np.abs(g_w))
+
+
+def test_adjoint_matches_stored_finite_differences():
+    """The oracle's adjoint on the full differentiation workload (256 planes,
+    2048 free taper samples, window loss) against the stored central
+    differences of the oracle's forward (tests/golden/make_grad_fd.py):
+    every w-coordinate (O(h^2) truncation, about 3e-6), 32 taper
+    coordinates and 16 directions (the loss is quadratic in the taper, so
+    these differences are exact up to rounding)."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "grad_fd.json")) as f:
+        fd = json.load(f)
+    wl = W.grad()
+    tau = wl.taper.astype(np.float64)
+    caches, _ = H.generate(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, tau, wl.w,
+                           wl.support, 1, "cubic")
+    _, g = A.energy_outside_loss(caches, wl.support, wl.oversampling, fd["inner_half"])
+    gt, gw = A.grad(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, tau, wl.w,
+                    wl.support, g, 1, "cubic")
+    coords = np.asarray(fd["tau_coords"])
+    assert np.array_equal(coords, W.fd_taper_coords(wl.n_radial))
+    assert np.max(np.abs(gw - np.asarray(fd["w_fd"]))) <= 1e-5 * np.max(np.abs(gw))
+    assert np.max(np.abs(gt[coords] - np.asarray(fd["tau_fd"]))) <= 1e-10 * np.max(np.abs(gt))
+    d_fd = np.asarray(fd["direction_fd"])
+    assert np.max(np.abs(W.fd_directions(wl.n_radial) @ gt - d_fd) / np.abs(d_fd)) <= 1e-8
