@@ -717,6 +717,10 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
 
   const size_t mElems = (size_t)g.rowsPad * g.NrPad;
   if ((s = pl->alloc(&g.M32, mElems, "M32")) != WKERN_OK) return s;
+  // split plans: M's BF16 terms in the node-group-major layout the hybrid
+  // variant stages
+  if (g.precision == 1 && (s = pl->alloc(&g.MsplitG, mElems * 3, "MsplitG")) != WKERN_OK)
+    return s;
   // the FP32 screen serves the FP32 path and the split path's FP32-operand
   // variants; the BF16 terms of M and of the screen, which only the other
   // split variants read, are built when such a variant is selected

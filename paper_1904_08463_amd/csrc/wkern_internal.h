@@ -67,7 +67,11 @@ enum ContractVariant {
   kRingF64x256 = 8,
   // the 64 x 256 FP32-operand ring on 8 waves of 32 x 64 (two waves per SIMD)
   kRingF64x256W8 = 9,
-  kNumVariants = 10
+  // split-BF16 only: M as its plan-time BF16 terms (group-major MsplitG),
+  // the FP32 screen split in registers; 8 waves of 64 rows x 32 columns, so
+  // every screen value is split by one wave and M by none
+  kRingH64x256 = 10,
+  kNumVariants = 11
 };
 
 // Tile geometry of a variant: rows per tile = 32 * rb, columns per tile.
@@ -79,6 +83,7 @@ struct ContractShape {
 ContractShape contract_shape(int variant);
 // The BF16-term ring variants exist for the split-BF16 contraction only.
 inline bool variant_supported(int precision, int variant) {
+  if (variant == kRingH64x256) return precision == 1;
   return variant < kRing128x128 || variant >= kRingF128x128 || precision == 1;
 }
 // Whether a variant reads the FP32 screen (B32) rather than its BF16 terms.
@@ -107,6 +112,7 @@ struct DevPlan {
   double* phi;            // [NrPad]
   float* M32;             // [rowsPad][NrPad]
   uint16_t* Msplit;       // [rowsPad][NrPad/8][3][8]
+  uint16_t* MsplitG;      // [NrPad/8][3][rowsPad][8]: the same terms, node-group major
   int32_t* perm;          // [P] sorted j -> caller p
   int32_t* nrhoSorted;    // [P]
   int32_t* lineOffSorted; // [P + 1]

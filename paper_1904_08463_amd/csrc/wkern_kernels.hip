@@ -48,7 +48,7 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
 // --------------------------------------------------------------------------
 __global__ void k_hankel_matrix(int rowsPad, int NrPad, int Nr, int nrhoMax, double dr,
                                 double drho, float* __restrict__ M32,
-                                uint16_t* __restrict__ Msplit) {
+                                uint16_t* __restrict__ Msplit, uint16_t* __restrict__ MsplitG) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;
   if (i >= NrPad || k >= rowsPad) return;
@@ -59,16 +59,25 @@ __global__ void k_hankel_matrix(int rowsPad, int NrPad, int Nr, int nrhoMax, dou
     m = kTwoPi * j0(kTwoPi * rho * r) * r * dr;
   }
   M32[(size_t)k * NrPad + i] = (float)m;
-  if (!Msplit) return;  // the BF16 terms are built only for the variants that read them
+  if (!Msplit && !MsplitG) return;  // terms only for the variants that read them
   const uint16_t t0 = bf16_rne((float)m);
   double rem = m - (double)bf16_to_f(t0);
   const uint16_t t1 = bf16_rne((float)rem);
   rem -= (double)bf16_to_f(t1);
   const uint16_t t2 = bf16_rne((float)rem);
-  const size_t base = ((size_t)k * (NrPad / 8) + (i >> 3)) * 24 + (i & 7);
-  Msplit[base] = t0;
-  Msplit[base + 8] = t1;
-  Msplit[base + 16] = t2;
+  if (Msplit) {
+    const size_t base = ((size_t)k * (NrPad / 8) + (i >> 3)) * 24 + (i & 7);
+    Msplit[base] = t0;
+    Msplit[base + 8] = t1;
+    Msplit[base + 16] = t2;
+  }
+  if (MsplitG) {
+    const size_t gterm = (size_t)rowsPad * 8;  // one term of one node group
+    const size_t base = (size_t)(i >> 3) * 3 * gterm + (size_t)k * 8 + (i & 7);
+    MsplitG[base] = t0;
+    MsplitG[base + gterm] = t1;
+    MsplitG[base + 2 * gterm] = t2;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -1077,6 +1086,206 @@ __global__ __launch_bounds__(64 * WR * WC) void k_contract_bf16x6_ringf(
 }
 
 // --------------------------------------------------------------------------
+// Split-BF16 contraction with M taken as its plan-time BF16 terms (split from
+// the FP64 value, node-group-major layout MsplitG[i/8][term][row][8]) and the
+// FP32 screen split in registers.  A workgroup of 8 waves computes 64 rows x
+// 256 columns; wave w owns columns 32 w .. 32 w + 31 for all 64 rows (two
+// 32x32 blocks), so every screen value is split by exactly one wave and no
+// wave converts M.  A stage of 16 nodes holds M's terms as [group][term][row]
+// (16 bytes a row: consecutive lanes read consecutive LDS quads) and the
+// screen columns as four 16-byte quarters each, XOR-swizzled as in the FP32
+// ring.  The stage is 22 KB, so 7 stages fit in LDS (6 in flight).  The
+// products, their order and the FP64 combine are the other split variants'.
+// --------------------------------------------------------------------------
+template <int NS>
+__global__ __launch_bounds__(512) void k_contract_bf16x6_ringh(
+    const Tile* __restrict__ tiles, int NrPad, int rowsPad, int kchunk, int P, int lineTotal,
+    const uint4* __restrict__ MsplitG, const float* __restrict__ B32,
+    const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
+    double* __restrict__ part) {
+  constexpr int BM = 64, BN = 256, NT = 512, RB = 2;
+  constexpr int AU = 2 * 3 * BM;          // uint4 of M terms per stage
+  constexpr int SU = AU + BN * 4;         // plus the screen quarters
+  constexpr int LF = SU / NT;             // full load rounds of every wave
+  constexpr int RW = (SU - LF * NT) / 64; // waves issuing one more round
+  constexpr int LW = LF + (RW > 0 ? 1 : 0);
+  static_assert(SU % 64 == 0 && AU % 64 == 0, "whole waves per region");
+  static_assert(LW * (NS - 2) < 64, "too many loads in flight for vmcnt");
+  static_assert(NS == 7, "ring depth");
+  __shared__ uint4 ring0[SU];
+  __shared__ uint4 ring1[SU];
+  __shared__ uint4 ring2[SU];
+  __shared__ uint4 ring3[SU];
+  __shared__ uint4 ring4[SU];
+  __shared__ uint4 ring5[SU];
+  __shared__ uint4 ring6[SU];
+
+  const Tile t = tiles[blockIdx.x];
+  if (t.row0 < 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+
+  // source of slot position u = NT l + tid and its advance per stage (bytes)
+  const char* src[LW];
+  int adv[LW];
+#pragma unroll
+  for (int l = 0; l < LW; ++l) {
+    int u = NT * l + tid;
+    if (u >= SU) u = 0;  // waves past the last partial round: never issued
+    if (u < AU) {
+      const int grp = u / (3 * BM);
+      const int term = (u / BM) % 3;
+      const int row = u % BM;
+      src[l] = (const char*)(MsplitG + ((size_t)(t.k0 / 8 + grp) * 3 + term) * rowsPad + t.row0 +
+                             row);
+      adv[l] = 2 * 3 * rowsPad * 16;
+    } else {
+      const int c = (u - AU) >> 2;
+      const int qd = ((u - AU) & 3) ^ ((c >> 2) & 3);
+      src[l] = (const char*)(B32 + (size_t)(t.col0 + c) * NrPad + t.k0 + 4 * qd);
+      adv[l] = 64;
+    }
+  }
+  const int nst = kchunk / 16;  // a multiple of 16
+
+  double accd[RB][16];
+  f32x16 hi[RB], lo[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accd[b][r] = 0.0;
+      hi[b][r] = 0.f;
+      lo[b][r] = 0.f;
+    }
+
+  auto slot_of = [&](auto kc) -> uint4* {
+    constexpr int K = decltype(kc)::value;
+    if constexpr (K == 0) return ring0;
+    else if constexpr (K == 1) return ring1;
+    else if constexpr (K == 2) return ring2;
+    else if constexpr (K == 3) return ring3;
+    else if constexpr (K == 4) return ring4;
+    else if constexpr (K == 5) return ring5;
+    else return ring6;
+  };
+  auto issue = [&](auto kc, int stage) {
+    uint4* slot = slot_of(kc);
+#pragma unroll
+    for (int l = 0; l < LW; ++l)
+      if (l < LF || wave < RW)  // wave-uniform
+        __builtin_amdgcn_global_load_lds((const void*)(src[l] + (size_t)stage * adv[l]),
+                                         (__attribute__((address_space(3))) void*)(slot + NT * l +
+                                                                                   64 * wave),
+                                         16, 0, 0);
+  };
+  auto barrier = [&]() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  const int col = 32 * wave + rr;  // this lane's column in the tile
+  const int sw = (col >> 2) & 3;
+  auto step = [&](auto kc, int s) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int KN = (K + NS - 1) % NS;
+    if (s + NS - 2 < nst) {
+      if (RW == 0 || wave < RW)
+        wait_vmcnt<LW * (NS - 2)>();
+      else
+        wait_vmcnt<LF * (NS - 2)>();
+    } else {
+      wait_vmcnt<0>();
+    }
+    barrier();
+    if (s + NS - 1 < nst) issue(std::integral_constant<int, KN>{}, s + NS - 1);
+    const uint4* slot = slot_of(kc);
+    // the 8 nodes hb*8 .. hb*8 + 7 of this lane's column, split into terms
+    bf16x8 bq[3];
+    {
+      const float4* bs = (const float4*)(slot + AU);
+      const float4 a = bs[4 * col + ((2 * hb) ^ sw)];
+      const float4 b = bs[4 * col + ((2 * hb + 1) ^ sw)];
+      split_bf16x3(a, b, bq[0], bq[1], bq[2]);
+    }
+    bf16x8 aq[RB][3];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int term = 0; term < 3; ++term)
+        aq[rb][term] = as_bf16x8(slot[(hb * 3 + term) * BM + rb * 32 + rr]);
+#pragma unroll
+    for (int term = 0; term < 6; ++term) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        switch (term) {
+          case 0: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[2], lo[rb], 0, 0, 0); break;
+          case 1: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[1], lo[rb], 0, 0, 0); break;
+          case 2: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[0], lo[rb], 0, 0, 0); break;
+          case 3: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[1], lo[rb], 0, 0, 0); break;
+          case 4: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[0], lo[rb], 0, 0, 0); break;
+          default: hi[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[0], hi[rb], 0, 0, 0); break;
+        }
+      }
+    }
+    if (((s + 1) * 16) % kSubChunk == 0) {
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          accd[b][r] += (double)hi[b][r] + (double)lo[b][r];
+          hi[b][r] = 0.f;
+          lo[b][r] = 0.f;
+        }
+    }
+  };
+
+  issue(std::integral_constant<int, 0>{}, 0);
+  issue(std::integral_constant<int, 1>{}, 1);
+  issue(std::integral_constant<int, 2>{}, 2);
+  issue(std::integral_constant<int, 3>{}, 3);
+  issue(std::integral_constant<int, 4>{}, 4);
+  issue(std::integral_constant<int, 5>{}, 5);
+  // nst is a multiple of 16: two full rounds of the 7 slots, then a tail
+  int s0 = 0;
+  for (; s0 + NS <= nst; s0 += NS) {
+    step(std::integral_constant<int, 0>{}, s0);
+    step(std::integral_constant<int, 1>{}, s0 + 1);
+    step(std::integral_constant<int, 2>{}, s0 + 2);
+    step(std::integral_constant<int, 3>{}, s0 + 3);
+    step(std::integral_constant<int, 4>{}, s0 + 4);
+    step(std::integral_constant<int, 5>{}, s0 + 5);
+    step(std::integral_constant<int, 6>{}, s0 + 6);
+  }
+  // the remaining nst - s0 < 7 stages, starting at slot 0
+  if (s0 < nst) step(std::integral_constant<int, 0>{}, s0);
+  if (s0 + 1 < nst) step(std::integral_constant<int, 1>{}, s0 + 1);
+  if (s0 + 2 < nst) step(std::integral_constant<int, 2>{}, s0 + 2);
+  if (s0 + 3 < nst) step(std::integral_constant<int, 3>{}, s0 + 3);
+  if (s0 + 4 < nst) step(std::integral_constant<int, 4>{}, s0 + 4);
+  if (s0 + 5 < nst) step(std::integral_constant<int, 5>{}, s0 + 5);
+
+  const int gcol = t.col0 + col;
+  const int j = gcol >> 1;
+  const int comp = gcol & 1;
+  if (j >= P || j >= t.pad[0]) return;
+  const int nr = nrhoSorted[j];
+  double* dst = part + ((size_t)t.kc * lineTotal + lineOffSorted[j]) * 2 + comp;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    if (rb >= t.rbN) break;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = t.row0 + rb * 32 + 8 * (r >> 2) + 4 * hb + (r & 3);
+      if (row < nr) dst[(size_t)row * 2] = accd[rb][r];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // FP32 contraction through the same FP32 ring: v_mfma_f32_32x32x2f32, FP32
 // sums over kSubChunk nodes added to FP64 running sums.
 // --------------------------------------------------------------------------
@@ -1998,7 +2207,7 @@ __global__ __launch_bounds__(kPsThreads) void k_ps_lines(
 hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s) {
   dim3 grid((p.NrPad + 255) / 256, p.rowsPad);
   hipLaunchKernelGGL(k_hankel_matrix, grid, dim3(256), 0, s, p.rowsPad, p.NrPad, p.Nr,
-                     p.nrhoMax, p.dr, p.drho, p.M32, p.Msplit);
+                     p.nrhoMax, p.dr, p.drho, p.M32, p.Msplit, p.MsplitG);
   return hipGetLastError();
 }
 
@@ -2034,6 +2243,7 @@ ContractShape contract_shape(int variant) {
     case kRingF128x128: return ContractShape{4, 128, 1};
     case kRingF64x256: return ContractShape{2, 256, 1};
     case kRingF64x256W8: return ContractShape{2, 256, 1};
+    case kRingH64x256: return ContractShape{2, 256, 1};
     default: return ContractShape{1, 512, 1};  // kRing32x512
   }
 }
@@ -2130,6 +2340,12 @@ hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int
         hipLaunchKernelGGL((k_contract_bf16x6_ringf<2, 4, 1, 2, 8>), g, dim3(512), 0, s, tiles,
                            p.NrPad, p.kchunk, p.P, p.lineTotal, p.M32, p.B32, p.nrhoSorted,
                            p.lineOffSorted, p.part);
+        break;
+      case kRingH64x256:
+        if (!p.MsplitG) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_contract_bf16x6_ringh<7>), g, dim3(512), 0, s, tiles, p.NrPad,
+                           p.rowsPad, p.kchunk, p.P, p.lineTotal, (const uint4*)p.MsplitG, p.B32,
+                           p.nrhoSorted, p.lineOffSorted, p.part);
         break;
       default:
         hipLaunchKernelGGL((k_contract_bf16x6_ring<1, 4, 1, 4, 3>), g, dim3(256), 0, s, tiles,
