@@ -408,6 +408,20 @@ wkern_status wkern_wpartition(const double* w, int64_t n_records, int32_t n_plan
                               size_t workspace_bytes, int32_t* order, int64_t* plane_start,
                               double* w_plane, void* stream);
 
+/* -------------------------------------------------------------------------
+ * Diagnostics.
+ * ------------------------------------------------------------------------- */
+
+/* Store ceiling of the device, for comparison with the resample's HBM write
+ * rate (its bound): writes `bytes` of zeros to buf (device, 16-byte aligned,
+ * bytes a positive multiple of 16) in one of the store structures a kernel
+ * writer can take.  pattern 0: one 16-byte store per lane, after which the
+ * wave ends (blocks of 256 lanes in address order; the fastest plain-store
+ * structure measured on this device); pattern 1: the resample's structure, a
+ * block of 256 lanes walking a 512 KB unit in 4 KB steps.  Asynchronous on
+ * `stream`.  Errors: INVALID_ARG, DEVICE. */
+wkern_status wkern_store_ceiling(void* buf, int64_t bytes, int32_t pattern, void* stream);
+
 /* wkern_wpartition without a workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation): the keys, record indices and sort storage live in

@@ -5,5 +5,5 @@ The compute path is the HIP library ``libwkern.so`` (C ABI in
 it in a ``torch.autograd.Function``.
 """
 from .wkern import (ABI_VERSION, EXPORTS, FFT2DPlan, Plan, WkernError,  # noqa: F401
-                    layout_desc, load_library, wpartition, wpartition_noalloc,
+                    layout_desc, load_library, store_ceiling, wpartition, wpartition_noalloc,
                     wpartition_workspace)

@@ -26,6 +26,7 @@ SOURCES = [
     ("wkern_resample.hip", True),
     ("wkern_wpartition.hip", True),
     ("wkern_grid.hip", True),
+    ("wkern_diag.hip", True),
 ]
 LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
 

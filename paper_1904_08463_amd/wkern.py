@@ -38,6 +38,7 @@ EXPORTS = (
     "wkern_strerror", "wkern_last_error",
     "wkern_fft2d_plan", "wkern_fft2d_generate", "wkern_fft2d_destroy",
     "wkern_wpartition_workspace", "wkern_wpartition", "wkern_wpartition_noalloc",
+    "wkern_store_ceiling",
     "wkern_prepare_lines", "wkern_grid",
 )
 
@@ -135,6 +136,8 @@ def load_library() -> ctypes.CDLL:
     lib.wkern_wpartition.restype = ctypes.c_int
     lib.wkern_wpartition.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, vp, ctypes.c_size_t, vp, vp, vp, vp]
+    lib.wkern_store_ceiling.restype = ctypes.c_int
+    lib.wkern_store_ceiling.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp]
     lib.wkern_wpartition_noalloc.restype = ctypes.c_int
     lib.wkern_wpartition_noalloc.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_int32, vp, vp, vp, vp]
@@ -546,3 +549,17 @@ def wpartition_noalloc(w, n_planes: int, absolute: bool = True, stat: str = "mea
             _ptr(w), n, int(n_planes), 1 if absolute else 0, WSTAT[stat], _ptr(order),
             _ptr(plane_start), _ptr(w_plane), _stream_handle(stream)))
     return order, plane_start, w_plane
+
+
+STORE_PATTERNS = {"one_store_per_lane": 0, "unit_walk": 1}
+
+
+def store_ceiling(buf, pattern: str = "one_store_per_lane", stream=None):
+    """Write zeros over the device tensor buf with the given store structure
+    (diagnostic: the device's store ceilings, for the resample's roofline)."""
+    import torch
+    if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.is_contiguous()):
+        raise ValueError("buf must be a contiguous device tensor")
+    nbytes = buf.numel() * buf.element_size()
+    _check(load_library().wkern_store_ceiling(_ptr(buf), nbytes - nbytes % 16,
+                                              STORE_PATTERNS[pattern], _stream_handle(stream)))

@@ -268,3 +268,22 @@ def test_output_guard_regions_untouched(truncated, make):
     if not truncated:
         _check_against_oracle(plan, host[guard:guard + total], wl, 1e-6)
     plan.close()
+
+
+def test_store_ceiling_diagnostic():
+    """wkern_store_ceiling writes zeros over the buffer in both store
+    structures and rejects misaligned or partial sizes."""
+    import ctypes
+    from paper_1904_08463_amd import load_library, store_ceiling
+    buf = torch.full((3 * 65536 * 2 + 48,), 7.0, dtype=torch.float32, device="cuda")
+    for pattern in ("one_store_per_lane", "unit_walk"):
+        buf.fill_(7.0)
+        store_ceiling(buf, pattern)
+        assert torch.count_nonzero(buf).item() == 0
+    lib = load_library()
+    p = ctypes.c_void_p(buf.data_ptr())
+    assert lib.wkern_store_ceiling(p, 24, 0, None) == 1          # not a multiple of 16
+    assert lib.wkern_store_ceiling(ctypes.c_void_p(buf.data_ptr() + 4), 16, 0, None) == 1
+    assert lib.wkern_store_ceiling(p, 16, 2, None) == 1          # unknown pattern
+    assert lib.wkern_store_ceiling(None, 16, 0, None) == 1
+    torch.cuda.synchronize()
