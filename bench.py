@@ -111,9 +111,14 @@ def _contraction_roofline(plan, wl, stages, precision):
     ms = stages["contraction"]
     achieved = executed / (ms * 1e-3) / 1e12
     peak = MFMA_PEAK_TFLOPS[precision]
-    return {"bound": "mfma", "kernel": "k_contract_*", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "algorithmic_flop": flop,
-            "executed_flop": executed, "ms": ms}
+    res = {"bound": "mfma", "kernel": "k_contract_*", "achieved": achieved, "peak": peak,
+           "unit": "TFLOP/s", "frac": achieved / peak, "algorithmic_flop": flop,
+           "executed_flop": executed, "ms": ms}
+    if precision == "bf16x6":
+        # the split contraction's utilisation target and how far it is from it
+        res["target_frac"] = 0.60
+        res["ms_at_target"] = executed / (0.60 * peak * 1e12) * 1e3
+    return res
 
 
 def _fft_paths(wl, taper, w, out, steps):
