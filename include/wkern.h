@@ -60,8 +60,18 @@
  *   the site after the variable took this value fails once: "alloc" (a device
  *   allocation of the library: OUT_OF_MEMORY), "launch" (a kernel launch of a
  *   generating call: DEVICE), "capture" (the graph capture of wkern_generate:
- *   DEVICE).  A failed call releases what it allocated and leaves the plan
- *   usable.
+ *   DEVICE), "canary" (the canary check of wkern_sync_status finds one byte
+ *   changed, written there by the host).  A failed call releases what it
+ *   allocated and leaves the plan usable.
+ * - WKERN_CANARY=1 (debug, read by wkern_plan): every device allocation of
+ *   the plan, including the scratch allocated on the first truncated,
+ *   gradient and gridding calls, gets a 1 KiB guard band of 0xA5 bytes on
+ *   each side; wkern_sync_status compares all of them with the pattern and
+ *   returns DEVICE naming the buffer whose band changed (an overrun of the
+ *   library's own scratch).  The caller's output has no band inside it:
+ *   plane blocks are contiguous, so an overrun of one lands in its
+ *   neighbour, and around the whole buffer the caller can place its own.
+ *   Costs 2 KiB per allocation and a synchronous check per status read.
  */
 #ifndef WKERN_H
 #define WKERN_H
@@ -320,7 +330,10 @@ wkern_status wkern_set_chunks(wkern_plan_t plan, int32_t chunks);
  * clears it.  WKERN_OK: no flag since the last read.  WKERN_ERR_NONFINITE: a
  * generating call since then produced a non-finite radial-line value; the
  * detail (wkern_last_error) names the first affected plane in caller order,
- * and the affected planes' caches are unspecified.  Not allowed while
+ * and the affected planes' caches are unspecified.  With canaries on
+ * (WKERN_CANARY) it first waits for the whole device and checks every guard
+ * band: DEVICE, with the buffer named, if one changed (the band is refilled,
+ * so the next read reports later overruns only).  Not allowed while
  * `stream` is being captured (INVALID_ARG).  Errors: INVALID_ARG, DEVICE. */
 wkern_status wkern_sync_status(wkern_plan_t plan, void* stream);
 

@@ -209,7 +209,19 @@ struct wkern_plan_s {
   std::vector<int32_t> mirStart;      // [P + 1]
   std::vector<int32_t> mirList;       // mirrored planes grouped by source
   DevPlan dp{};
-  std::vector<void*> allocations;
+  // Every device allocation of the plan.  With canaries on (WKERN_CANARY at
+  // plan creation) each one carries a guard band of kGuardBytes of
+  // kGuardByte on both sides, checked by wkern_sync_status.
+  struct Allocation {
+    void* user;
+    void* raw;
+    size_t bytes;
+    const char* what;
+  };
+  std::vector<Allocation> allocations;
+  bool canary = false;
+  static constexpr size_t kGuardBytes = 1024;
+  static constexpr unsigned char kGuardByte = 0xA5;
 
   // pipeline chunks over the sorted planes
   int nChunks = 1;
@@ -269,7 +281,7 @@ struct wkern_plan_s {
     if (evJoinStore) (void)hipEventDestroy(evJoinStore);
     if (sCompute) (void)hipStreamDestroy(sCompute);
     if (sStore) (void)hipStreamDestroy(sStore);
-    for (void* ptr : allocations) (void)hipFree(ptr);
+    for (const Allocation& a : allocations) (void)hipFree(a.raw);
   }
 
   template <class T>
@@ -280,22 +292,36 @@ struct wkern_plan_s {
       *ptr = nullptr;
       return fail(WKERN_ERR_OUT_OF_MEMORY, "%s: injected allocation failure (WKERN_FAULT)", what);
     }
-    hipError_t e = hipMalloc(&raw, bytes);
+    const size_t guard = canary ? kGuardBytes : 0;
+    hipError_t e = hipMalloc(&raw, bytes + 2 * guard);
     if (e != hipSuccess) {
       *ptr = nullptr;
       return hip_fail(e, what);
     }
-    allocations.push_back(raw);
-    *ptr = (T*)raw;
+    if (guard) {
+      // the whole block, so the guards hold the pattern before any kernel runs
+      e = hipMemset(raw, kGuardByte, bytes + 2 * guard);
+      if (e != hipSuccess) {
+        (void)hipFree(raw);
+        *ptr = nullptr;
+        return hip_fail(e, "canary fill");
+      }
+    }
+    void* user = (unsigned char*)raw + guard;
+    allocations.push_back({user, raw, bytes, what});
+    *ptr = (T*)user;
     return WKERN_OK;
   }
 
   template <class T>
   void release(T*& ptr) {
     if (!ptr) return;
-    auto it = std::find(allocations.begin(), allocations.end(), (void*)ptr);
-    if (it != allocations.end()) allocations.erase(it);
-    (void)hipFree((void*)ptr);
+    auto it = std::find_if(allocations.begin(), allocations.end(),
+                           [&](const Allocation& a) { return a.user == (void*)ptr; });
+    if (it != allocations.end()) {
+      (void)hipFree(it->raw);
+      allocations.erase(it);
+    }
     ptr = nullptr;
   }
 
@@ -813,6 +839,10 @@ wkern_status wkern_plan(const wkern_desc* d, wkern_plan_t* out) {
   DeviceGuard guard(d->device);
   wkern_plan_s* pl = new (std::nothrow) wkern_plan_s();
   if (!pl) return fail(WKERN_ERR_OUT_OF_MEMORY, "plan allocation");
+  {
+    const char* env = std::getenv("WKERN_CANARY");
+    pl->canary = env && std::atoi(env) != 0;
+  }
   try {
     s = build_plan(d, pl);
   } catch (const std::bad_alloc&) {
@@ -1252,6 +1282,38 @@ wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
   return WKERN_OK;
 }
 
+// Compare every guard band of the plan's allocations with the fill pattern
+// after the device has drained.  The first changed band is reported (and
+// refilled, so that a later check starts clean); WKERN_FAULT=canary changes
+// one byte of the first allocation's trailing band first, from the host,
+// to test this path without an overrun.
+static wkern_status check_canaries(wkern_plan_t plan) {
+  using A = wkern_plan_s;
+  WK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  if (!plan->allocations.empty() && fault_hit("canary")) {
+    const A::Allocation& a = plan->allocations.front();
+    const unsigned char bad = (unsigned char)~A::kGuardByte;
+    WK_HIP(hipMemcpy((unsigned char*)a.user + a.bytes + 7, &bad, 1, hipMemcpyHostToDevice),
+           "canary fault");
+  }
+  std::vector<unsigned char> band(A::kGuardBytes);
+  for (const A::Allocation& a : plan->allocations) {
+    unsigned char* sides[2] = {(unsigned char*)a.raw, (unsigned char*)a.user + a.bytes};
+    for (int side = 0; side < 2; ++side) {
+      WK_HIP(hipMemcpy(band.data(), sides[side], A::kGuardBytes, hipMemcpyDeviceToHost),
+             "canary read");
+      size_t k = 0;
+      while (k < A::kGuardBytes && band[k] == A::kGuardByte) ++k;
+      if (k == A::kGuardBytes) continue;
+      WK_HIP(hipMemset(sides[side], A::kGuardByte, A::kGuardBytes), "canary refill");
+      return fail(WKERN_ERR_DEVICE,
+                  "canary overwritten %s the %s buffer (%zu bytes): byte %zu of the guard band",
+                  side ? "after" : "before", a.what, a.bytes, k);
+    }
+  }
+  return WKERN_OK;
+}
+
 wkern_status wkern_sync_status(wkern_plan_t plan, void* stream) {
   clear_error();
   if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
@@ -1265,6 +1327,10 @@ wkern_status wkern_sync_status(wkern_plan_t plan, void* stream) {
   WK_HIP(hipMemcpyAsync(word, plan->dp.status, sizeof(word), hipMemcpyDeviceToHost, st),
          "status read");
   WK_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (plan->canary) {
+    wkern_status cs2 = check_canaries(plan);
+    if (cs2 != WKERN_OK) return cs2;
+  }
   if (word[0] == 0) return WKERN_OK;
   const int32_t clear[2] = {0, INT32_MAX};
   WK_HIP(hipMemcpy(plan->dp.status, clear, sizeof(clear), hipMemcpyHostToDevice), "status clear");

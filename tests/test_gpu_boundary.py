@@ -287,3 +287,64 @@ def test_store_ceiling_diagnostic():
     assert lib.wkern_store_ceiling(p, 16, 2, None) == 1          # unknown pattern
     assert lib.wkern_store_ceiling(None, 16, 0, None) == 1
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# debug canaries around the plan's own allocations
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,variant", [("bf16x6", "ringh64x256"), ("bf16x6", "wave32x64"),
+                                               ("fp32", None)])
+def test_canaries_hold_on_every_path(env, precision, variant):
+    """WKERN_CANARY=1: every allocation of the plan carries guard bands.
+    After the plain (graph and eager), truncated, radial-line, gradient,
+    gridding and projection-slice calls on ragged supports at os 3, none
+    changed, and the caches still match the oracle; a byte changed by the
+    host hook is reported with the buffer named, and the band is refilled."""
+    from paper_1904_08463_amd import Plan, wpartition
+    from paper_1904_08463_amd.wkern import WkernError
+    wl = W.random_small(11, n_planes=23, n_radial=333, os_=3, max_support=25)
+    env("WKERN_CANARY", "1")
+    print(f"case canaries {precision} {variant}", flush=True)
+    plan = Plan.from_workload(wl, precision=precision)
+    env("WKERN_CANARY", None)
+    if variant is not None:
+        plan.set_variant(variant)
+    taper, w = _inputs(wl)
+    for graph in (True, False):
+        plan.set_graph(graph)
+        flat = plan.generate(taper, w).cpu().numpy()
+        plan.sync_status()
+        _check_against_oracle(plan, flat, wl, 1e-6 if precision == "bf16x6" else 1e-5)
+    plan.generate_truncated(taper, w, 0.01)
+    plan.generate_radial(taper, w)
+    plan.sync_status()
+    g = torch.ones(int(plan.offsets[-1]), dtype=torch.complex64, device="cuda")
+    plan.grad(taper, w, g)
+    plan.sync_status()
+    # gridding: records spread over the planes' w range, fused and from the cache
+    rng = np.random.default_rng(5)
+    n, n_rec = 256, 4000
+    du = 1.0 / (wl.image_size * wl.cellsize)
+    rec_w = rng.uniform(wl.w.min(), wl.w.max(), n_rec)
+    uv = rng.uniform(-0.4 * n * du, 0.4 * n * du, (2, n_rec))
+    vis = (rng.standard_normal(n_rec) + 1j * rng.standard_normal(n_rec)).astype(np.complex64)
+    order_d, start_d, wp_d = wpartition(torch.from_numpy(rec_w).cuda(), wl.n_planes)
+    sup_d = plan.prepare_lines(taper, wp_d)
+    args = tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (uv[0], uv[1], rec_w, vis))
+    plan.grid(*args, order_d, start_d, sup_d, torch.zeros((n, n), dtype=torch.complex64, device="cuda"))
+    cache = plan.generate(taper, wp_d)
+    plan.grid(*args, order_d, start_d, sup_d, torch.zeros((n, n), dtype=torch.complex64, device="cuda"),
+              cache=cache, cache_offsets=torch.from_numpy(plan.offsets).cuda())
+    plan.sync_status()
+    plan.set_engine("projection_slice", "per_plane")
+    plan.generate(taper, w)
+    plan.sync_status()
+    plan.set_engine("matrix")
+    # the detection path, through a byte the host changes in a guard band
+    env("WKERN_FAULT", "canary")
+    with pytest.raises(WkernError) as ei:
+        plan.sync_status()
+    env("WKERN_FAULT", None)
+    assert ei.value.status == DEVICE and "canary overwritten after" in str(ei.value), str(ei.value)
+    plan.sync_status()  # refilled
+    plan.close()
