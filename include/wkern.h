@@ -103,7 +103,9 @@ typedef enum {
  * registers after the operands are staged.  (The BF16-term variants, which
  * wkern_set_variant can select, stage terms split from M's FP64 value and
  * from the FP32 screen value.)  Both paths accumulate in FP32 over sub-chunks
- * of 128 radial nodes and add the sub-chunk sums in FP64. */
+ * of 128 radial nodes and add the sub-chunk sums in FP64; one split-BF16
+ * variant (ringr64x256) keeps that running sum as an FP32 pair instead,
+ * formed with an exact two-sum (about 48 bits; measured at the same error). */
 typedef enum { WKERN_PREC_FP32 = 0, WKERN_PREC_BF16X6 = 1 } wkern_precision;
 
 /* Interpolation of the radial line (section 4.3.2). */
@@ -313,9 +315,12 @@ wkern_status wkern_plan_info(wkern_plan_t plan, int32_t* variant, int32_t* n_var
 wkern_status wkern_set_graph(wkern_plan_t plan, int32_t enable);
 
 /* Override the autotuner's choice of contraction variant (0 <= variant <
- * n_variants).  All variants compute the same sums in the same order per
- * output element.  The autotuner's candidates are the variants that stage
- * FP32 operands; selecting a split-BF16 variant that stages BF16 terms
+ * n_variants).  All variants compute the same products in the same order
+ * per output element; they differ in tiling, in how operands reach LDS and,
+ * for ringr64x256, in the running sum (an FP32 two-sum pair instead of FP64),
+ * so results can differ in the last bits.  The autotuner's candidates are
+ * the variants that stage FP32 operands or M's plan-time BF16 terms with the
+ * FP32 screen; selecting a split-BF16 variant that stages BF16 terms
  * builds those terms (M's and a screen buffer) on its first selection
  * (synchronous then).  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant);

@@ -71,7 +71,10 @@ enum ContractVariant {
   // the FP32 screen split in registers; 8 waves of 64 rows x 32 columns, so
   // every screen value is split by one wave and M by none
   kRingH64x256 = 10,
-  kNumVariants = 11
+  // the same tile with operands staged through registers and the running
+  // sum held as an FP32 two-sum pair (split-BF16 only)
+  kRingR64x256 = 11,
+  kNumVariants = 12
 };
 
 // Tile geometry of a variant: rows per tile = 32 * rb, columns per tile.
@@ -83,7 +86,7 @@ struct ContractShape {
 ContractShape contract_shape(int variant);
 // The BF16-term ring variants exist for the split-BF16 contraction only.
 inline bool variant_supported(int precision, int variant) {
-  if (variant == kRingH64x256) return precision == 1;
+  if (variant == kRingH64x256 || variant == kRingR64x256) return precision == 1;
   return variant < kRing128x128 || variant >= kRingF128x128 || precision == 1;
 }
 // Whether a variant reads the FP32 screen (B32) rather than its BF16 terms.

@@ -1286,6 +1286,245 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringh(
 }
 
 // --------------------------------------------------------------------------
+// The tile, wave mapping and products of the ring above, with the operands
+// staged through registers and a lighter running sum.  Each thread loads its
+// share of a stage with 16-byte global loads three stages ahead and writes
+// it to one of three LDS slots one stage ahead: this path streams the tile
+// operands faster than the direct-to-LDS loads.  The registers it needs come
+// from the accumulation.  The 00 product still sums on the matrix cores in
+// FP32 over kSubChunk nodes, but the running sum is an FP32 pair (big, comp)
+// instead of an FP64 value: at each flush big + hi is formed with an exact
+// two-sum and its rounding error added to comp, and the five small products
+// accumulate on the matrix cores straight into comp (they are 2^-8 of the
+// 00 product and smaller, comp's own rounding is below the pair's).  Three
+// registers per output instead of four; the result is big + comp in FP64.
+// --------------------------------------------------------------------------
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N - 1>), in order.
+template <int N, class F>
+__device__ __forceinline__ void unroll_steps(F&& f) {
+  if constexpr (N > 0) {
+    unroll_steps<N - 1>(f);
+    f(std::integral_constant<int, N - 1>{});
+  }
+}
+
+__device__ __forceinline__ void two_sum_into(float& big, float& comp, float hi) {
+  const float s = big + hi;
+  const float bp = s - big;
+  const float e = (big - (s - bp)) + (hi - bp);
+  big = s;
+  comp += e;
+}
+
+__global__ __launch_bounds__(512) void k_contract_bf16x6_ringr(
+    const Tile* __restrict__ tiles, int NrPad, int rowsPad, int kchunk, int P, int lineTotal,
+    const uint4* __restrict__ MsplitG, const float* __restrict__ B32,
+    const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
+    double* __restrict__ part) {
+  constexpr int BM = 64, BN = 256, NT = 512, RB = 2;
+  constexpr int AU = 2 * 3 * BM;          // uint4 of M terms per stage
+  constexpr int SU = AU + BN * 4;         // plus the screen quarters
+  constexpr int LF = SU / NT;             // full load rounds of every wave
+  constexpr int RW = (SU - LF * NT) / 64; // waves loading one more item
+  constexpr int LW = LF + (RW > 0 ? 1 : 0);
+  static_assert(SU % 64 == 0 && AU % 64 == 0, "whole waves per region");
+  // a slot holds LW full rounds, so that every thread stores its LW items
+  // (the waves past the last partial round into the tail, never read)
+  __shared__ uint4 slot0[NT * LW];
+  __shared__ uint4 slot1[NT * LW];
+  __shared__ uint4 slot2[NT * LW];
+
+  const Tile t = tiles[blockIdx.x];
+  if (t.row0 < 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+
+  // item u = NT l + tid of a stage: its source and its advance per stage
+  const char* src[LW];
+  int adv[LW];
+#pragma unroll
+  for (int l = 0; l < LW; ++l) {
+    int u = NT * l + tid;
+    if (u >= SU) u = 0;  // waves past the last partial round: loaded, not stored
+    if (u < AU) {
+      const int grp = u / (3 * BM);
+      const int term = (u / BM) % 3;
+      const int row = u % BM;
+      src[l] = (const char*)(MsplitG + ((size_t)(t.k0 / 8 + grp) * 3 + term) * rowsPad + t.row0 +
+                             row);
+      adv[l] = 2 * 3 * rowsPad * 16;
+    } else {
+      const int c = (u - AU) >> 2;
+      const int qd = ((u - AU) & 3) ^ ((c >> 2) & 3);
+      src[l] = (const char*)(B32 + (size_t)(t.col0 + c) * NrPad + t.k0 + 4 * qd);
+      adv[l] = 64;
+    }
+  }
+  const int nst = kchunk / 16;  // a multiple of 16
+
+  f32x16 hi[RB], comp[RB];
+  float big[RB][16];
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      hi[b][r] = 0.f;
+      comp[b][r] = 0.f;
+      big[b][r] = 0.f;
+    }
+
+  // the three register sets, named directly (a pointer to them would put
+  // them in scratch memory)
+  uint4 rg0[LW], rg1[LW], rg2[LW];
+  auto slot_of = [&](auto kc) __attribute__((always_inline)) -> uint4* {
+    constexpr int K = decltype(kc)::value;
+    if constexpr (K == 0) return slot0;
+    else if constexpr (K == 1) return slot1;
+    else return slot2;
+  };
+  // Every wave issues LW loads and LW LDS stores per stage,
+  // unconditionally: the compiler's load counting then sees the same number
+  // of loads between a register set's load and its use on every path (a
+  // conditional load makes it wait for all of them), and a step has no
+  // branch to cut its scheduling.  The waves past the last partial round
+  // load item 0's source again and store it past the stage; the stages past
+  // the end are clamped to the last one and never read.
+  auto load = [&](auto kc, int stage) __attribute__((always_inline)) {
+    constexpr int K = decltype(kc)::value;
+#pragma unroll
+    for (int l = 0; l < LW; ++l) {
+      const uint4 v = *(const uint4*)(src[l] + (size_t)stage * adv[l]);
+      if constexpr (K == 0) rg0[l] = v;
+      else if constexpr (K == 1) rg1[l] = v;
+      else rg2[l] = v;
+    }
+  };
+  auto store = [&](auto kc) __attribute__((always_inline)) {
+    constexpr int K = decltype(kc)::value;
+    uint4* slot = slot_of(kc);
+#pragma unroll
+    for (int l = 0; l < LW; ++l) {
+      if constexpr (K == 0) slot[NT * l + tid] = rg0[l];
+      else if constexpr (K == 1) slot[NT * l + tid] = rg1[l];
+      else slot[NT * l + tid] = rg2[l];
+    }
+  };
+  auto barrier = [&]() __attribute__((always_inline)) {
+    // the stage's LDS writes are complete; register loads stay in flight
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) only
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  const int col = 32 * wave + rr;  // this lane's column in the tile
+  const int sw = (col >> 2) & 3;
+  // The lane's 8 screen values of a stage, split into terms: two sets
+  // alternate, so that stage s + 1's values are read and split while the
+  // MFMAs of stage s run.  M's terms need no arithmetic and are read for the
+  // current stage only.
+  bf16x8 bq0[3], bq1[3], aq[RB][3];
+  auto read_b = [&](auto kc, auto fc) __attribute__((always_inline)) {
+    constexpr int F = decltype(fc)::value;
+    const float4* bs = (const float4*)(slot_of(kc) + AU);
+    const float4 x = bs[4 * col + ((2 * hb) ^ sw)];
+    const float4 y = bs[4 * col + ((2 * hb + 1) ^ sw)];
+    if constexpr (F == 0) split_bf16x3(x, y, bq0[0], bq0[1], bq0[2]);
+    else split_bf16x3(x, y, bq1[0], bq1[1], bq1[2]);
+  };
+  auto read_a = [&](auto kc) __attribute__((always_inline)) {
+    const uint4* slot = slot_of(kc);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int term = 0; term < 3; ++term)
+        aq[rb][term] = as_bf16x8(slot[(hb * 3 + term) * BM + rb * 32 + rr]);
+  };
+  auto mfma = [&](auto fc) __attribute__((always_inline)) {
+    constexpr int F = decltype(fc)::value;
+    auto& bq = F == 0 ? bq0 : bq1;
+#pragma unroll
+    for (int term = 0; term < 6; ++term) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        switch (term) {
+          case 0: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[2], comp[rb], 0, 0, 0); break;
+          case 1: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[1], comp[rb], 0, 0, 0); break;
+          case 2: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[0], comp[rb], 0, 0, 0); break;
+          case 3: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[1], comp[rb], 0, 0, 0); break;
+          case 4: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[0], comp[rb], 0, 0, 0); break;
+          default: hi[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[0], hi[rb], 0, 0, 0); break;
+        }
+      }
+    }
+  };
+  // Step s (K = s mod 24; slot and register set s mod 3, screen terms
+  // s mod 2, flush every 8 steps): stage s + 1 goes from its registers to
+  // its slot and the registers take stage s + 4; after the barrier both
+  // stage s and stage s + 1 are in LDS, so stage s + 1's screen values are
+  // read and split while the MFMAs of stage s (on values split one step
+  // earlier) run.  A slot is rewritten two steps after its last read, past
+  // a barrier.  The loop is unrolled over 24 steps so that every step is
+  // straight-line code (no branch to keep the split apart from the MFMAs):
+  // the last steps store, load and split a clamped stage they never use.
+  auto step = [&](auto kc, int s) __attribute__((always_inline)) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int SN = (K + 1) % 3;
+    constexpr int FC = K % 2, FN = 1 - FC;
+    store(std::integral_constant<int, SN>{});
+    load(std::integral_constant<int, SN>{}, min(s + 4, nst - 1));
+    barrier();
+    read_a(std::integral_constant<int, K % 3>{});
+    read_b(std::integral_constant<int, SN>{}, std::integral_constant<int, FN>{});
+    mfma(std::integral_constant<int, FC>{});
+    if constexpr ((K + 1) % (kSubChunk / 16) == 0) {
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          float c = comp[b][r];
+          two_sum_into(big[b][r], c, hi[b][r]);
+          comp[b][r] = c;
+          hi[b][r] = 0.f;
+        }
+    }
+  };
+  static_assert(24 % (kSubChunk / 16) == 0, "flush period divides the unrolled steps");
+
+  load(std::integral_constant<int, 0>{}, 0);
+  load(std::integral_constant<int, 1>{}, 1);
+  load(std::integral_constant<int, 2>{}, 2);
+  store(std::integral_constant<int, 0>{});
+  load(std::integral_constant<int, 0>{}, 3);
+  barrier();
+  read_b(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+  int s0 = 0;
+  for (; s0 + 24 <= nst; s0 += 24)
+    unroll_steps<24>([&](auto kc) __attribute__((always_inline)) { step(kc, s0 + decltype(kc)::value); });
+  unroll_steps<23>([&](auto kc) __attribute__((always_inline)) {
+    if (s0 + decltype(kc)::value < nst) step(kc, s0 + decltype(kc)::value);
+  });
+
+  const int gcol = t.col0 + col;
+  const int j = gcol >> 1;
+  const int cmp = gcol & 1;
+  if (j >= P || j >= t.pad[0]) return;
+  const int nr = nrhoSorted[j];
+  double* dst = part + ((size_t)t.kc * lineTotal + lineOffSorted[j]) * 2 + cmp;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    if (rb >= t.rbN) break;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = t.row0 + rb * 32 + 8 * (r >> 2) + 4 * hb + (r & 3);
+      if (row < nr) dst[(size_t)row * 2] = (double)big[rb][r] + (double)comp[rb][r];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // FP32 contraction through the same FP32 ring: v_mfma_f32_32x32x2f32, FP32
 // sums over kSubChunk nodes added to FP64 running sums.
 // --------------------------------------------------------------------------
@@ -2244,6 +2483,7 @@ ContractShape contract_shape(int variant) {
     case kRingF64x256: return ContractShape{2, 256, 1};
     case kRingF64x256W8: return ContractShape{2, 256, 1};
     case kRingH64x256: return ContractShape{2, 256, 1};
+    case kRingR64x256: return ContractShape{2, 256, 1};
     default: return ContractShape{1, 512, 1};  // kRing32x512
   }
 }
@@ -2344,6 +2584,12 @@ hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int
       case kRingH64x256:
         if (!p.MsplitG) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_contract_bf16x6_ringh<7>), g, dim3(512), 0, s, tiles, p.NrPad,
+                           p.rowsPad, p.kchunk, p.P, p.lineTotal, (const uint4*)p.MsplitG, p.B32,
+                           p.nrhoSorted, p.lineOffSorted, p.part);
+        break;
+      case kRingR64x256:
+        if (!p.MsplitG) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_contract_bf16x6_ringr, g, dim3(512), 0, s, tiles, p.NrPad,
                            p.rowsPad, p.kchunk, p.P, p.lineTotal, (const uint4*)p.MsplitG, p.B32,
                            p.nrhoSorted, p.lineOffSorted, p.part);
         break;
