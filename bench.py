@@ -702,6 +702,20 @@ def main():
     paths["precision_config"] = _guarded(_precision_config)
     ok = acc["bf16x6"]["accuracy_ok"]
 
+    # the split path's speed-up over the FP32 Hankel path and over 2D-FFT
+    # generation, same GPU, same run (time ratios, > 1 means the split path
+    # is faster)
+    def ratio(other, key="ms_per_step"):
+        v = paths.get(other, {}).get(key)
+        return v / ms if v else None
+    speedups = {"vs_fp32_hankel_step": ratio("fp32"),
+                "vs_2d_fft_per_plane_workspace": ratio("fft2d_per_plane"),
+                "vs_2d_fft_fixed_workspace": ratio("fft2d_max_support")}
+    c16 = stages.get("contraction")
+    c32 = paths.get("fp32", {}).get("stage_ms", {}).get("contraction")
+    speedups["vs_fp32_hankel_contraction"] = c32 / c16 if c16 and c32 else None
+    combine = ("fp32 two-sum pair" if info["variant"] == "ringr64x256" else "fp64")
+
     line = {
         "metric": "w-kernels/sec at <=1e-6 rel err (split-BF16 Hankel; FP32 Hankel beside it)",
         # the metric counts kernels only when the timed cache meets its gate
@@ -716,7 +730,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x6 (fp32 accumulate, fp64 combine)",
+        "dtype": f"bf16x6 (fp32 accumulate, {combine} combine)",
         "data": "synthetic",
         "config": {"workload": "batch: 16 ch x 1024 w-planes, Nr 8192, os 8, S 7..255, "
                                "2048^2 @ 3.5 arcsec, PSWF taper; 16384 kernels per step, "
@@ -729,6 +743,7 @@ def main():
                      # the same 30.6 GB written with plain stores on this device
                      "peak_measured": ceilings.get("one_store_per_lane", {}).get("GB/s"),
                      "store_ceilings": ceilings},
+        "speedups": speedups,
         "paths": paths,
         "machine": _machine(),
     }
