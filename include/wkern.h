@@ -105,7 +105,8 @@ typedef enum {
  * from the FP32 screen value.)  Both paths accumulate in FP32 over sub-chunks
  * of 128 radial nodes and add the sub-chunk sums in FP64; one split-BF16
  * variant (ringr64x256) keeps that running sum as an FP32 pair instead,
- * formed with an exact two-sum (about 48 bits; measured at the same error). */
+ * formed with an exact two-sum (about 48 bits; measured at the same error),
+ * and so does ringw64x256. */
 typedef enum { WKERN_PREC_FP32 = 0, WKERN_PREC_BF16X6 = 1 } wkern_precision;
 
 /* Interpolation of the radial line (section 4.3.2). */
@@ -317,7 +318,8 @@ wkern_status wkern_set_graph(wkern_plan_t plan, int32_t enable);
 /* Override the autotuner's choice of contraction variant (0 <= variant <
  * n_variants).  All variants compute the same products in the same order
  * per output element; they differ in tiling, in how operands reach LDS and,
- * for ringr64x256, in the running sum (an FP32 two-sum pair instead of FP64),
+ * for ringr64x256 and ringw64x256, in the running sum (an FP32 two-sum pair
+ * instead of FP64),
  * so results can differ in the last bits.  The autotuner's candidates are
  * the variants that stage FP32 operands or M's plan-time BF16 terms with the
  * FP32 screen; selecting a split-BF16 variant that stages BF16 terms

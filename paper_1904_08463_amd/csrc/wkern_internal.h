@@ -74,7 +74,11 @@ enum ContractVariant {
   // the same tile with operands staged through registers and the running
   // sum held as an FP32 two-sum pair (split-BF16 only)
   kRingR64x256 = 11,
-  kNumVariants = 12
+  // the same with the screen loaded straight into registers by the lanes
+  // that use it and M's terms through a deep LDS ring, one barrier every 4
+  // stages (split-BF16 only)
+  kRingW64x256 = 12,
+  kNumVariants = 13
 };
 
 // Tile geometry of a variant: rows per tile = 32 * rb, columns per tile.
@@ -86,7 +90,8 @@ struct ContractShape {
 ContractShape contract_shape(int variant);
 // The BF16-term ring variants exist for the split-BF16 contraction only.
 inline bool variant_supported(int precision, int variant) {
-  if (variant == kRingH64x256 || variant == kRingR64x256) return precision == 1;
+  if (variant == kRingH64x256 || variant == kRingR64x256 || variant == kRingW64x256)
+    return precision == 1;
   return variant < kRing128x128 || variant >= kRingF128x128 || precision == 1;
 }
 // Whether a variant reads the FP32 screen (B32) rather than its BF16 terms.

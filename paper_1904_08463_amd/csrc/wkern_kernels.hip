@@ -1525,6 +1525,197 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringr(
 }
 
 // --------------------------------------------------------------------------
+// The tile, wave mapping, products and two-sum running sum of the kernel
+// above, with the waves loosely coupled.  The screen columns go straight
+// from global memory into the registers of the lane that uses them (a lane
+// owns one column and 8 nodes of each 16-node stage), four stages ahead, so
+// the screen needs neither LDS nor a barrier.  Only M's terms, which all 8
+// waves share, go through LDS: every thread loads one 16-byte item of a
+// stage into registers three stages before it writes it to a ring of 8
+// slots, 4 stages before the stage is used, and the workgroup meets at a
+// barrier once every 4 stages.  Between barriers the waves drift apart, so
+// one wave's split and loads overlap another's MFMAs on the same SIMD.
+// Stage t is written at step t - 4 and read at step t: a barrier ends one of
+// the steps t - 4 .. t - 1, after the write (RAW); its slot was last read at
+// step t - 8, and a barrier ends one of the steps t - 8 .. t - 5 (WAR).  No
+// direct-to-LDS loads: the compiler's load counting stays exact.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_contract_bf16x6_ringw(
+    const Tile* __restrict__ tiles, int NrPad, int rowsPad, int kchunk, int P, int lineTotal,
+    const uint4* __restrict__ MsplitG, const float* __restrict__ B32,
+    const int32_t* __restrict__ nrhoSorted, const int32_t* __restrict__ lineOffSorted,
+    double* __restrict__ part) {
+  constexpr int BM = 64, NT = 512, RB = 2;
+  constexpr int AU = 2 * 3 * BM;  // uint4 of M terms per stage (384)
+  constexpr int NSL = 8;          // M slots
+  constexpr int AHEAD = 4;        // stages between a slot's write and its read
+  constexpr int PERIOD = 4;       // stages per barrier
+  static_assert(AHEAD >= PERIOD && NSL >= AHEAD + PERIOD, "ring arithmetic");
+  // one uint4 per thread per stage: the waves past the M terms store item 0
+  // again into the slot's tail, never read
+  __shared__ uint4 ringA[NSL][NT];
+
+  const Tile t = tiles[blockIdx.x];
+  if (t.row0 < 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int hb = lane >> 5;
+  const int rr = lane & 31;
+  const int nst = kchunk / 16;  // a multiple of 16
+
+  // M terms: item u = tid of a stage and its advance per stage (bytes)
+  const char* srcA;
+  {
+    const int u = tid < AU ? tid : 0;
+    const int grp = u / (3 * BM);
+    const int term = (u / BM) % 3;
+    const int row = u % BM;
+    srcA = (const char*)(MsplitG + ((size_t)(t.k0 / 8 + grp) * 3 + term) * rowsPad + t.row0 + row);
+  }
+  const size_t advA = (size_t)2 * 3 * rowsPad * 16;
+  // this lane's screen column, nodes hb * 8 .. hb * 8 + 7 of each stage
+  const int col = 32 * wave + rr;
+  const float4* srcB = (const float4*)(B32 + (size_t)(t.col0 + col) * NrPad + t.k0 + 8 * hb);
+
+  f32x16 hi[RB], comp[RB];
+  float big[RB][16];
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      hi[b][r] = 0.f;
+      comp[b][r] = 0.f;
+      big[b][r] = 0.f;
+    }
+
+  // register sets, named directly: M items three stages ahead of their
+  // LDS write, raw screen values four stages ahead of their split
+  uint4 ra0, ra1, ra2;
+  float4 b0x, b0y, b1x, b1y, b2x, b2y, b3x, b3y;
+  auto load_a = [&](auto kc, int stage) __attribute__((always_inline)) {
+    constexpr int K = decltype(kc)::value;
+    const uint4 v = *(const uint4*)(srcA + (size_t)stage * advA);
+    if constexpr (K == 0) ra0 = v;
+    else if constexpr (K == 1) ra1 = v;
+    else ra2 = v;
+  };
+  auto store_a = [&](auto kc, int slotIdx) __attribute__((always_inline)) {
+    constexpr int K = decltype(kc)::value;
+    if constexpr (K == 0) ringA[slotIdx][tid] = ra0;
+    else if constexpr (K == 1) ringA[slotIdx][tid] = ra1;
+    else ringA[slotIdx][tid] = ra2;
+  };
+  auto load_b = [&](auto kc, int stage) __attribute__((always_inline)) {
+    constexpr int K = decltype(kc)::value;
+    const float4 x = srcB[4 * stage];
+    const float4 y = srcB[4 * stage + 1];
+    if constexpr (K == 0) { b0x = x; b0y = y; }
+    else if constexpr (K == 1) { b1x = x; b1y = y; }
+    else if constexpr (K == 2) { b2x = x; b2y = y; }
+    else { b3x = x; b3y = y; }
+  };
+  auto barrier = [&]() __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS writes and reads
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+
+  // Step s (K = s mod 24): the M item of stage s + 4 goes from its
+  // registers to its slot and the registers take stage s + 7; the raw
+  // screen values of stage s are split and their registers take stage
+  // s + 4; then the MFMAs of stage s.
+  auto step = [&](auto kc, int s) __attribute__((always_inline)) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int SA = K % 3, SB = K % 4;
+    // nothing moves across a step boundary: left free over the 4 steps
+    // between barriers, the scheduler sinks each load next to its use
+    __builtin_amdgcn_sched_barrier(0);
+    store_a(std::integral_constant<int, SA>{}, (K + AHEAD) % NSL);
+    load_a(std::integral_constant<int, SA>{}, min(s + AHEAD + 3, nst - 1));
+    bf16x8 bq[3];
+    if constexpr (SB == 0) split_bf16x3(b0x, b0y, bq[0], bq[1], bq[2]);
+    else if constexpr (SB == 1) split_bf16x3(b1x, b1y, bq[0], bq[1], bq[2]);
+    else if constexpr (SB == 2) split_bf16x3(b2x, b2y, bq[0], bq[1], bq[2]);
+    else split_bf16x3(b3x, b3y, bq[0], bq[1], bq[2]);
+    load_b(std::integral_constant<int, SB>{}, min(s + 4, nst - 1));
+    const uint4* slot = ringA[K % NSL];
+    bf16x8 aq[RB][3];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int term = 0; term < 3; ++term)
+        aq[rb][term] = as_bf16x8(slot[(hb * 3 + term) * BM + rb * 32 + rr]);
+#pragma unroll
+    for (int term = 0; term < 6; ++term) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        switch (term) {
+          case 0: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[2], comp[rb], 0, 0, 0); break;
+          case 1: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[1], comp[rb], 0, 0, 0); break;
+          case 2: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[0], comp[rb], 0, 0, 0); break;
+          case 3: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[1], comp[rb], 0, 0, 0); break;
+          case 4: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[0], comp[rb], 0, 0, 0); break;
+          default: hi[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[0], hi[rb], 0, 0, 0); break;
+        }
+      }
+    }
+    if constexpr ((K + 1) % (kSubChunk / 16) == 0) {
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          float c = comp[b][r];
+          two_sum_into(big[b][r], c, hi[b][r]);
+          comp[b][r] = c;
+          hi[b][r] = 0.f;
+        }
+    }
+    if constexpr ((K + 1) % PERIOD == 0) barrier();
+  };
+  static_assert(24 % (kSubChunk / 16) == 0 && 24 % NSL == 0 && 24 % PERIOD == 0 && 24 % 3 == 0,
+                "the unrolled steps repeat every slot, set and flush pattern");
+
+  // prologue: M stages 0 .. 3 in their slots, stages 4 .. 6 in registers,
+  // screen stages 0 .. 3 in registers
+  for (int st = 0; st < AHEAD; ++st)
+    ringA[st][tid] = *(const uint4*)(srcA + (size_t)min(st, nst - 1) * advA);
+  load_a(std::integral_constant<int, 0>{}, min(AHEAD, nst - 1));
+  load_a(std::integral_constant<int, 1>{}, min(AHEAD + 1, nst - 1));
+  load_a(std::integral_constant<int, 2>{}, min(AHEAD + 2, nst - 1));
+  load_b(std::integral_constant<int, 0>{}, 0);
+  load_b(std::integral_constant<int, 1>{}, 1);
+  load_b(std::integral_constant<int, 2>{}, 2);
+  load_b(std::integral_constant<int, 3>{}, 3);
+  barrier();
+  int s0 = 0;
+  for (; s0 + 24 <= nst; s0 += 24)
+    unroll_steps<24>([&](auto kc) __attribute__((always_inline)) {
+      step(kc, s0 + decltype(kc)::value);
+    });
+  unroll_steps<23>([&](auto kc) __attribute__((always_inline)) {
+    if (s0 + decltype(kc)::value < nst) step(kc, s0 + decltype(kc)::value);
+  });
+
+  const int gcol = t.col0 + col;
+  const int j = gcol >> 1;
+  const int cmp = gcol & 1;
+  if (j >= P || j >= t.pad[0]) return;
+  const int nr = nrhoSorted[j];
+  double* dst = part + ((size_t)t.kc * lineTotal + lineOffSorted[j]) * 2 + cmp;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    if (rb >= t.rbN) break;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = t.row0 + rb * 32 + 8 * (r >> 2) + 4 * hb + (r & 3);
+      if (row < nr) dst[(size_t)row * 2] = (double)big[rb][r] + (double)comp[rb][r];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // FP32 contraction through the same FP32 ring: v_mfma_f32_32x32x2f32, FP32
 // sums over kSubChunk nodes added to FP64 running sums.
 // --------------------------------------------------------------------------
@@ -2484,6 +2675,7 @@ ContractShape contract_shape(int variant) {
     case kRingF64x256W8: return ContractShape{2, 256, 1};
     case kRingH64x256: return ContractShape{2, 256, 1};
     case kRingR64x256: return ContractShape{2, 256, 1};
+    case kRingW64x256: return ContractShape{2, 256, 1};
     default: return ContractShape{1, 512, 1};  // kRing32x512
   }
 }
@@ -2590,6 +2782,12 @@ hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int
       case kRingR64x256:
         if (!p.MsplitG) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_contract_bf16x6_ringr, g, dim3(512), 0, s, tiles, p.NrPad,
+                           p.rowsPad, p.kchunk, p.P, p.lineTotal, (const uint4*)p.MsplitG, p.B32,
+                           p.nrhoSorted, p.lineOffSorted, p.part);
+        break;
+      case kRingW64x256:
+        if (!p.MsplitG) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_contract_bf16x6_ringw, g, dim3(512), 0, s, tiles, p.NrPad,
                            p.rowsPad, p.kchunk, p.P, p.lineTotal, (const uint4*)p.MsplitG, p.B32,
                            p.nrhoSorted, p.lineOffSorted, p.part);
         break;

@@ -327,7 +327,7 @@ class Plan:
 
     VARIANTS = ("wave32x64", "wave32x128", "lds128x128", "lds64x256", "ring128x128",
                 "ring64x256", "ring32x512", "ringf128x128", "ringf64x256", "ringf64x256w8",
-                "ringh64x256", "ringr64x256")
+                "ringh64x256", "ringr64x256", "ringw64x256")
 
     def info(self):
         """Autotuner choice, candidate timings (ms) and pipeline chunk count."""

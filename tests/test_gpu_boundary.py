@@ -292,8 +292,9 @@ def test_store_ceiling_diagnostic():
 # ---------------------------------------------------------------------------
 # debug canaries around the plan's own allocations
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("precision,variant", [("bf16x6", "ringr64x256"), ("bf16x6", "ringh64x256"),
-                                               ("bf16x6", "wave32x64"), ("fp32", None)])
+@pytest.mark.parametrize("precision,variant", [("bf16x6", "ringw64x256"), ("bf16x6", "ringr64x256"),
+                                               ("bf16x6", "ringh64x256"), ("bf16x6", "wave32x64"),
+                                               ("fp32", None)])
 def test_canaries_hold_on_every_path(env, precision, variant):
     """WKERN_CANARY=1: every allocation of the plan carries guard bands.
     After the plain (graph and eager), truncated, radial-line, gradient,

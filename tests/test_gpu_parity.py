@@ -184,8 +184,9 @@ def test_batch_workload_full_size(precision):
 
 VARIANTS = ("wave32x64", "wave32x128", "lds128x128", "lds64x256", "ring128x128", "ring64x256",
             "ring32x512", "ringf128x128", "ringf64x256", "ringf64x256w8", "ringh64x256",
-            "ringr64x256")
-SPLIT_ONLY = ("ring128x128", "ring64x256", "ring32x512", "ringh64x256", "ringr64x256")
+            "ringr64x256", "ringw64x256")
+SPLIT_ONLY = ("ring128x128", "ring64x256", "ring32x512", "ringh64x256", "ringr64x256",
+              "ringw64x256")
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
