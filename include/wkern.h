@@ -319,10 +319,14 @@ wkern_status wkern_set_graph(wkern_plan_t plan, int32_t enable);
  * n_variants).  All variants compute the same products in the same order
  * per output element; they differ in tiling, in how operands reach LDS and,
  * for ringr64x256 and ringw64x256, in the running sum (an FP32 two-sum pair
- * instead of FP64),
- * so results can differ in the last bits.  The autotuner's candidates are
- * the variants that stage FP32 operands or M's plan-time BF16 terms with the
- * FP32 screen; selecting a split-BF16 variant that stages BF16 terms
+ * instead of FP64), so results can differ in the last bits.  The
+ * autotuner's candidates are the variants that stage FP32 operands or M's
+ * plan-time BF16 terms with the FP32 screen.  Indices: 0 wave32x64,
+ * 1 wave32x128, 2 lds128x128, 3 lds64x256, 4 ring128x128, 5 ring64x256,
+ * 6 ring32x512 (4-6 split-BF16 only), 7 ringf128x128, 8 ringf64x256,
+ * 9 ringf64x256w8, 10 ringh64x256, 11 ringr64x256, 12 ringw64x256 (10-12
+ * split-BF16 only); a variant the plan's precision cannot run is
+ * INVALID_ARG.  Selecting a split-BF16 variant that stages BF16 terms
  * builds those terms (M's and a screen buffer) on its first selection
  * (synchronous then).  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 wkern_status wkern_set_variant(wkern_plan_t plan, int32_t variant);
