@@ -213,6 +213,34 @@ def test_every_contraction_variant(variant, precision):
         plan.close()
 
 
+def test_two_sum_variants_agree():
+    """ringr64x256 and ringw64x256 run the same arithmetic in the same order
+    (only the way operands reach the lanes differs): their caches agree bit
+    for bit.  ringh64x256 keeps the running sum in FP64 instead of the FP32
+    two-sum pair: the radial lines agree to 1e-8 of each plane's peak, far
+    inside the 1e-6 gate (the emulated difference of the two sums is below
+    1e-9)."""
+    wl = W.paper()
+    plan = _plan(wl, "bf16x6")
+    taper, w = _inputs(wl)
+    got = {}
+    lines = {}
+    for v in ("ringr64x256", "ringw64x256", "ringh64x256"):
+        plan.set_variant(v)
+        got[v] = plan.generate(taper, w).cpu().numpy()
+        lines[v] = plan.generate_radial(taper, w).cpu().numpy()
+    assert np.array_equal(got["ringr64x256"].view(np.uint64), got["ringw64x256"].view(np.uint64))
+    loffs = np.concatenate([[0], np.cumsum(plan.nrho)])
+    worst = 0.0
+    for p in range(wl.n_planes):
+        a = lines["ringr64x256"][loffs[p]:loffs[p + 1]]
+        b = lines["ringh64x256"][loffs[p]:loffs[p + 1]]
+        worst = max(worst, float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+    print(f"two-sum vs FP64 running sum: worst line difference {worst:.3e}", flush=True)
+    assert worst <= 1e-8
+    plan.close()
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
 def test_pipeline_chunks_bitwise(precision):
     """Splitting the batch into pipeline chunks (the resample of one chunk
