@@ -883,7 +883,7 @@ static wkern_status enqueue_lines(wkern_plan_t plan, const float* taper, const d
   const DevPlan& g = plan->dp;
   if (plan->engine == WKERN_ENGINE_MATRIX) {
     const int v = plan->variant;
-    WK_LAUNCH(launch_screen(g, 0, g.P, taper, w, variant_fp32_screen(g.precision, v), st),
+    WK_LAUNCH(launch_screen(g, 0, g.P, taper, w, screen_layout(g.precision, v), st),
            "screen launch");
     WK_LAUNCH(launch_contract(g, v, plan->d_tiles[v], plan->chunkT[v].back(), st),
            "contraction launch");
@@ -905,7 +905,7 @@ static wkern_status enqueue_chunk(wkern_plan_t plan, int c, const float* taper, 
   wkern_status s;
   if (plan->engine == WKERN_ENGINE_MATRIX) {
     if ((s = plan->record_begin(0, compute, &r)) != WKERN_OK) return s;
-    WK_LAUNCH(launch_screen(g, j0, j1, taper, w, variant_fp32_screen(g.precision, v), compute),
+    WK_LAUNCH(launch_screen(g, j0, j1, taper, w, screen_layout(g.precision, v), compute),
            "screen launch");
     if ((s = record_end(r, compute)) != WKERN_OK) return s;
     if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;

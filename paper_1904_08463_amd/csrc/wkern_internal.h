@@ -98,6 +98,15 @@ inline bool variant_supported(int precision, int variant) {
 inline bool variant_fp32_screen(int precision, int variant) {
   return precision == 0 || variant >= kRingF128x128;
 }
+// Layout of the screen a variant reads: its BF16 terms (Bsplit), the FP32
+// screen column-major (B32[col][NrPad]) or node-group-major
+// (B32[NrPad / 16][colsPad][16], so that the 16 nodes of a stage of all
+// columns are one contiguous block).
+enum ScreenLayout { kScreenTerms = 0, kScreenColumns = 1, kScreenGroups = 2 };
+inline ScreenLayout screen_layout(int precision, int variant) {
+  if (!variant_fp32_screen(precision, variant)) return kScreenTerms;
+  return variant == kRingW64x256 && precision == 1 ? kScreenGroups : kScreenColumns;
+}
 
 // Resample units: blocks of at most this many consecutive elements of one
 // plane (the full cache's units, and the truncated layout's).
@@ -133,7 +142,7 @@ struct DevPlan {
   ResampleUnit* units;
   int nUnits;
   // scratch
-  float* B32;             // [colsPad][NrPad]
+  float* B32;             // [colsPad][NrPad], or [NrPad/16][colsPad][16] (kScreenGroups)
   uint16_t* Bsplit;       // [colsPad][NrPad/8][3][8]
   double* part;           // [nkc][lineTotal][2]
   float4* coef;           // [lineTotal][2]
@@ -160,9 +169,9 @@ hipError_t launch_grad(const DevPlan& p, const GradScratch& gs, const float* tap
                        hipStream_t s);
 hipError_t launch_hankel_matrix(const DevPlan& p, hipStream_t s);
 hipError_t prepare_kernels(const DevPlan& p);
-// fp32: write the FP32 screen (B32) instead of its BF16 terms (Bsplit).
+// Write the screen of sorted planes [j0, j1) in the given layout.
 hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, const double* w,
-                         bool fp32, hipStream_t s);
+                         ScreenLayout layout, hipStream_t s);
 hipError_t launch_contract(const DevPlan& p, int variant, const Tile* tiles, int nTiles,
                            hipStream_t s);
 hipError_t launch_spline(const DevPlan& p, int j0, int j1, hipStream_t s, double frac = 0.0,

@@ -18,7 +18,7 @@ hipError_t launch_grad(const DevPlan&, const GradScratch&, const float*, const d
                        const void*, float*, double*, hipStream_t) { unreachable("launch_grad"); }
 hipError_t launch_hankel_matrix(const DevPlan&, hipStream_t) { unreachable("launch_hankel_matrix"); }
 hipError_t prepare_kernels(const DevPlan&) { unreachable("prepare_kernels"); }
-hipError_t launch_screen(const DevPlan&, int, int, const float*, const double*, bool,
+hipError_t launch_screen(const DevPlan&, int, int, const float*, const double*, ScreenLayout,
                          hipStream_t) { unreachable("launch_screen"); }
 hipError_t launch_contract(const DevPlan&, int, const Tile*, int, hipStream_t) {
   unreachable("launch_contract");
