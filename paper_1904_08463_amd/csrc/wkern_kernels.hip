@@ -138,37 +138,50 @@ __global__ __launch_bounds__(256) void k_screen_f32(int j0, int j1, int Nr, int 
 }
 
 // FP32 screen, node-group-major: B32[i / 16][c][i % 16] with c = 2 j + re/im
-// (colsPad columns a group).  A thread computes the 16 nodes of one group
-// for one plane and writes its re and im rows as 128 contiguous bytes; the
-// 256 threads of a workgroup take consecutive planes, so a wave writes 8 KB
-// contiguously.  The group's phi and taper are the same for every thread.
+// (colsPad columns a group).  A workgroup takes one group of 16 nodes and
+// 64 kScreenPlaneRun planes; thread 4 jj + q holds nodes 4 q .. 4 q + 3 of
+// the group (their phi and taper loaded once) and walks planes jj, jj + 64,
+// ..., loading the next plane's w while it computes the current one.  For
+// each plane it writes the four values to the plane's re row and im row
+// with one 16-byte store each: the four threads of a plane fill its 128
+// contiguous bytes of the group, so a store instruction covers 16 planes'
+// halves of 128-byte lines and the next instruction the other halves.
+constexpr int kScreenPlaneRun = 8;
 __global__ __launch_bounds__(256) void k_screen_f32_groups(int j0, int j1, int Nr, int colsPad,
                                                            const int32_t* __restrict__ perm,
                                                            const double* __restrict__ phi,
                                                            const float* __restrict__ taper,
                                                            const double* __restrict__ w,
                                                            float* __restrict__ B32) {
-  const int j = j0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int q = (int)(threadIdx.x & 3);
   const int g = (int)blockIdx.y;
+  const int i0 = 16 * g + 4 * q;
+  int j = j0 + 64 * kScreenPlaneRun * (int)blockIdx.x + (int)(threadIdx.x >> 2);
   if (j >= j1) return;
-  const double wv = w[perm[j]];
-  float re[16], im[16];
+  double ph[4];
+  float ta[4];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int i = 16 * g + u;
-    re[u] = 0.f;
-    im[u] = 0.f;
-    if (i < Nr) {
-      const float2 v = screen_value(wv, phi[i], taper[i]);
-      re[u] = v.x;
-      im[u] = v.y;
-    }
+  for (int u = 0; u < 4; ++u) {
+    ph[u] = i0 + u < Nr ? phi[i0 + u] : 0.0;
+    ta[u] = i0 + u < Nr ? taper[i0 + u] : 0.f;
   }
-  float4* dst = (float4*)(B32 + ((size_t)g * colsPad + 2 * j) * 16);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    dst[q] = make_float4(re[4 * q], re[4 * q + 1], re[4 * q + 2], re[4 * q + 3]);
-    dst[4 + q] = make_float4(im[4 * q], im[4 * q + 1], im[4 * q + 2], im[4 * q + 3]);
+  const int jEnd = min(j1, j + 64 * kScreenPlaneRun);
+  double wv = w[perm[j]];
+  float* row = B32 + ((size_t)g * colsPad + 2 * j) * 16 + 4 * q;
+  while (j < jEnd) {
+    const int jn = j + 64;
+    const double wn = jn < jEnd ? w[perm[jn]] : 0.0;
+    float4 re = make_float4(0.f, 0.f, 0.f, 0.f), im = re;
+    float2 v;
+    if (i0 < Nr) { v = screen_value(wv, ph[0], ta[0]); re.x = v.x; im.x = v.y; }
+    if (i0 + 1 < Nr) { v = screen_value(wv, ph[1], ta[1]); re.y = v.x; im.y = v.y; }
+    if (i0 + 2 < Nr) { v = screen_value(wv, ph[2], ta[2]); re.z = v.x; im.z = v.y; }
+    if (i0 + 3 < Nr) { v = screen_value(wv, ph[3], ta[3]); re.w = v.x; im.w = v.y; }
+    *(float4*)row = re;
+    *(float4*)(row + 16) = im;
+    row += 64 * 2 * 16;
+    j = jn;
+    wv = wn;
   }
 }
 
@@ -2689,7 +2702,8 @@ hipError_t launch_screen(const DevPlan& p, int j0, int j1, const float* taper, c
                          ScreenLayout layout, hipStream_t s) {
   if (j1 <= j0) return hipSuccess;
   if (layout == kScreenGroups) {
-    dim3 grid((j1 - j0 + 255) / 256, p.NrPad / 16);
+    const int run = 64 * kScreenPlaneRun;
+    dim3 grid((j1 - j0 + run - 1) / run, p.NrPad / 16);
     hipLaunchKernelGGL(k_screen_f32_groups, grid, dim3(256), 0, s, j0, j1, p.Nr, p.colsPad,
                        p.perm, p.phi, taper, w, p.B32);
   } else if (layout == kScreenColumns) {
