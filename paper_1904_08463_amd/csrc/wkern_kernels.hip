@@ -1578,13 +1578,13 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringr(
 // major for this kernel (k_screen_f32_groups), goes straight from global
 // memory into the registers of the lane that uses it (a lane owns one column
 // and 8 nodes of each 16-node stage), four stages ahead, so it needs neither
-// LDS nor a barrier; in the node-group-major layout a wave's load covers 32
-// adjacent columns' 64 bytes, where the column-major layout scatters them
-// NrPad floats apart (measured: 0.25 against 0.30 ms for the same kernel).  Only M's terms, which all 8
-// waves share, go through LDS: every thread loads one 16-byte item of a
-// stage into registers three stages before it writes it to a ring of 8
-// slots, 4 stages before the stage is used, and the workgroup meets at a
-// barrier once every 4 stages.  Between barriers the waves drift apart, so
+// LDS nor a barrier.  In the node-group-major layout a wave's load covers 32
+// adjacent columns' 64 bytes; the column-major layout scatters them NrPad
+// floats apart, and the same kernel on it took 0.30 ms against 0.25.  Only
+// M's terms, which all 8 waves share, go through LDS: every thread loads one
+// 16-byte item of a stage into registers three stages before it writes it
+// to a ring of 8 slots, 4 stages before the stage is used, and the
+// workgroup meets at a barrier once every 4 stages.  Between barriers the waves drift apart, so
 // one wave's split and loads overlap another's MFMAs on the same SIMD.
 // Stage t is written at step t - 4 and read at step t: a barrier ends one of
 // the steps t - 4 .. t - 1, after the write (RAW); its slot was last read at
