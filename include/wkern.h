@@ -97,16 +97,15 @@ typedef enum {
 
 /* Arithmetic of the Hankel contraction (step 2).  The phase is always formed
  * in FP64.  FP32: M and s rounded to FP32, FP32 matrix-core products.
- * BF16X6: M and s rounded to FP32, each FP32 value split exactly into three
- * BF16 terms (x = x0 + x1 + x2) and the terms combined with six BF16
- * matrix-core products (02, 11, 20, 01, 10, 00); the split happens in
- * registers after the operands are staged.  (The BF16-term variants, which
- * wkern_set_variant can select, stage terms split from M's FP64 value and
- * from the FP32 screen value.)  Both paths accumulate in FP32 over sub-chunks
- * of 128 radial nodes and add the sub-chunk sums in FP64; one split-BF16
- * variant (ringr64x256) keeps that running sum as an FP32 pair instead,
- * formed with an exact two-sum (about 48 bits; measured at the same error),
- * and so does ringw64x256. */
+ * BF16X6: each operand as three BF16 terms (x = x0 + x1 + x2), combined
+ * with six BF16 matrix-core products (02, 11, 20, 01, 10, 00).  The
+ * screen's terms are an exact split of its FP32 value; M's terms are an
+ * exact split of its FP32 value (ringf variants) or split at plan time from
+ * its FP64 value (the others).  Both paths accumulate in FP32 over
+ * sub-chunks of 128 radial nodes; the sub-chunk sums go into an FP64
+ * running sum or, in ringr64x256 and ringw64x256 (the autotuner's usual
+ * choice), into an FP32 pair formed with an exact two-sum (about 48 bits;
+ * measured at the same error). */
 typedef enum { WKERN_PREC_FP32 = 0, WKERN_PREC_BF16X6 = 1 } wkern_precision;
 
 /* Interpolation of the radial line (section 4.3.2). */
