@@ -28,7 +28,7 @@ SOURCES = [
     ("wkern_grid.hip", True),
     ("wkern_diag.hip", True),
 ]
-LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
+LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def _run(cmd):

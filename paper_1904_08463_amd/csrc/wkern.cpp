@@ -4,6 +4,7 @@
 #include "wkern.h"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <array>
@@ -21,6 +22,18 @@
 #include <vector>
 
 #include "wkern_internal.h"
+
+namespace {
+// A roctx range over a scope (the entry points and, on the host side, the
+// enqueueing of each stage): visible to rocprofv3 --marker-trace, no cost
+// without a tool attached.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+}  // namespace
 
 using namespace wkern;
 
@@ -827,6 +840,7 @@ static wkern_status build_plan(const wkern_desc* d, wkern_plan_s* pl) {
 
 wkern_status wkern_plan(const wkern_desc* d, wkern_plan_t* out) {
   clear_error();
+  TraceRange tr("wkern_plan");
   if (!out) return fail(WKERN_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   wkern_status s = validate(d);
@@ -904,24 +918,34 @@ static wkern_status enqueue_chunk(wkern_plan_t plan, int c, const float* taper, 
   StageRecord* r;
   wkern_status s;
   if (plan->engine == WKERN_ENGINE_MATRIX) {
-    if ((s = plan->record_begin(0, compute, &r)) != WKERN_OK) return s;
-    WK_LAUNCH(launch_screen(g, j0, j1, taper, w, screen_layout(g.precision, v), compute),
-           "screen launch");
-    if ((s = record_end(r, compute)) != WKERN_OK) return s;
+    {
+      TraceRange tr("wkern screen");
+      if ((s = plan->record_begin(0, compute, &r)) != WKERN_OK) return s;
+      WK_LAUNCH(launch_screen(g, j0, j1, taper, w, screen_layout(g.precision, v), compute),
+             "screen launch");
+      if ((s = record_end(r, compute)) != WKERN_OK) return s;
+    }
+    TraceRange tr("wkern contraction");
     if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;
     WK_LAUNCH(launch_contract(g, v, plan->d_tiles[v] + t0, t1 - t0, compute), "contraction launch");
+    if ((s = record_end(r, compute)) != WKERN_OK) return s;
   } else {
+    TraceRange tr("wkern projection-slice lines");
     if ((s = plan->record_begin(1, compute, &r)) != WKERN_OK) return s;
     WK_LAUNCH(launch_ps_lines(g, plan->ps, j0, j1, taper, w, compute), "projection-slice launch");
+    if ((s = record_end(r, compute)) != WKERN_OK) return s;
   }
-  if ((s = record_end(r, compute)) != WKERN_OK) return s;
-  if ((s = plan->record_begin(2, compute, &r)) != WKERN_OK) return s;
-  WK_LAUNCH(launch_spline(lines_view(plan), j0, j1, compute), "spline launch");
-  if ((s = record_end(r, compute)) != WKERN_OK) return s;
+  {
+    TraceRange tr("wkern spline");
+    if ((s = plan->record_begin(2, compute, &r)) != WKERN_OK) return s;
+    WK_LAUNCH(launch_spline(lines_view(plan), j0, j1, compute), "spline launch");
+    if ((s = record_end(r, compute)) != WKERN_OK) return s;
+  }
   if (handoff) {
     WK_HIP(hipEventRecord(handoff, compute), "hipEventRecord");
     WK_HIP(hipStreamWaitEvent(store, handoff, 0), "hipStreamWaitEvent");
   }
+  TraceRange tr("wkern resample");
   if ((s = plan->record_begin(3, store, &r)) != WKERN_OK) return s;
   WK_LAUNCH(launch_resample(g, plan->chunkU[c], plan->chunkU[c + 1], out, store),
          "resample launch");
@@ -996,6 +1020,7 @@ static wkern_status capture_graph(wkern_plan_t plan, const float* taper, const d
 wkern_status wkern_generate(wkern_plan_t plan, const float* taper, const double* w, void* out,
                             void* stream) {
   clear_error();
+  TraceRange tr("wkern_generate");
   wkern_status s = check_gen_args(plan, taper, w, out);
   if (s != WKERN_OK) return s;
   DeviceGuard guard(plan->desc.device);
@@ -1046,6 +1071,7 @@ wkern_status wkern_generate_truncated(wkern_plan_t plan, const float* taper, con
                                       double frac, void* out, int64_t out_capacity,
                                       int32_t* support_out, int64_t* offsets_out, void* stream) {
   clear_error();
+  TraceRange tr("wkern_generate_truncated");
   wkern_status s = check_gen_args(plan, taper, w, out);
   if (s != WKERN_OK) return s;
   if (!support_out || !offsets_out) return fail(WKERN_ERR_INVALID_ARG, "layout output is NULL");
@@ -1066,6 +1092,7 @@ wkern_status wkern_generate_truncated(wkern_plan_t plan, const float* taper, con
 wkern_status wkern_prepare_lines(wkern_plan_t plan, const float* taper, const double* w,
                                  double frac, int32_t* support_out, void* stream) {
   clear_error();
+  TraceRange tr("wkern_prepare_lines");
   wkern_status s = check_gen_args(plan, taper, w, support_out);
   if (s != WKERN_OK) return s;
   if (!(frac >= 0.0 && frac < 1.0)) return fail(WKERN_ERR_INVALID_ARG, "frac %g not in [0, 1)", frac);
@@ -1087,6 +1114,7 @@ wkern_status wkern_grid(wkern_plan_t plan, const double* u, const double* v, con
                         const int64_t* cache_offsets, int32_t grid_size, void* grid,
                         void* stream) {
   clear_error();
+  TraceRange tr("wkern_grid");
   if (!plan) return fail(WKERN_ERR_INVALID_ARG, "plan is NULL");
   if (n_records < 0 || n_records > 0x7FFFFFFF)
     return fail(WKERN_ERR_INVALID_ARG, "n_records %lld out of range", (long long)n_records);
@@ -1235,6 +1263,7 @@ wkern_status wkern_set_chunks(wkern_plan_t plan, int32_t chunks) {
 wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const double* w,
                                    void* lines, void* stream) {
   clear_error();
+  TraceRange tr("wkern_generate_radial");
   wkern_status s = check_gen_args(plan, taper, w, lines);
   if (s != WKERN_OK) return s;
   DeviceGuard guard(plan->desc.device);
@@ -1247,6 +1276,7 @@ wkern_status wkern_generate_radial(wkern_plan_t plan, const float* taper, const 
 wkern_status wkern_grad(wkern_plan_t plan, const float* taper, const double* w,
                         const void* grad_out, float* grad_taper, double* grad_w, void* stream) {
   clear_error();
+  TraceRange tr("wkern_grad");
   wkern_status s = check_gen_args(plan, taper, w, grad_out);
   if (s != WKERN_OK) return s;
   if (!grad_taper || !grad_w) return fail(WKERN_ERR_INVALID_ARG, "gradient output is NULL");

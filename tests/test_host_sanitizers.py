@@ -23,7 +23,8 @@ def test_host_abi_under_sanitizers(tmp_path):
            f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
            os.path.join(CSRC, "wkern.cpp"), os.path.join(HERE, "launch_stubs.cpp"),
            os.path.join(HERE, "abi_check.cpp"),
-           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", exe]
+           "-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib",
+           "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-4000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
