@@ -561,9 +561,16 @@ def _machine():
     try:
         import torch
         info["torch"] = torch.__version__
+        info["hip_runtime"] = torch.version.hip
         info["gpu"] = torch.cuda.get_device_properties(0).gcnArchName
     except Exception:  # pragma: no cover
         pass
+    # the kernel driver's version, where the box exposes it
+    try:
+        with open("/sys/module/amdgpu/version") as fh:
+            info["amdgpu_driver"] = fh.read().strip() or None
+    except OSError:
+        info["amdgpu_driver"] = None
     import subprocess
     try:
         info["git_sha"] = subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True,
