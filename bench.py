@@ -495,6 +495,13 @@ def _cpu_fft_generator(wl, planes, workers, fixed):
     return time.perf_counter() - t0
 
 
+def parallel_efficiency(t_single, t_multi, cores):
+    """eta = speed-up / cores, the speed-up being the single-threaded time
+    over the multi-threaded one (section 6.8, the equation beside Table 2;
+    a fraction here, the paper prints percent)."""
+    return (t_single / t_multi) / cores
+
+
 def _cpu_baselines(wl, small):
     """Host-side comparison methods with single-thread and all-thread timings
     and the parallel efficiency eta = (t_1 / t_N) / N (section 6.8, Table 2).
@@ -509,7 +516,8 @@ def _cpu_baselines(wl, small):
     ta = time.perf_counter() - t0
     res["oracle"] = {"kernels_per_s_1_thread": len(small) / t1,
                      "kernels_per_s_all_threads": len(small) / ta,
-                     "blas_threads_all": int(_blas_threads()), "eta": (t1 / ta) / cores}
+                     "blas_threads_all": int(_blas_threads()),
+                     "eta": parallel_efficiency(t1, ta, cores)}
     fft_planes = small[::4]
     for fixed in (False, True):
         tag = "fft2d_fixed_workspace" if fixed else "fft2d_per_plane_workspace"
@@ -517,7 +525,7 @@ def _cpu_baselines(wl, small):
         t1f = _cpu_fft_generator(wl, fft_planes, 1, fixed)
         res[tag] = {"planes": int(len(fft_planes)), "kernels_per_s_all_threads": len(fft_planes) / ta,
                     "kernels_per_s_1_thread": len(fft_planes) / t1f,
-                    "eta": (t1f / ta) / cores}
+                    "eta": parallel_efficiency(t1f, ta, cores)}
     return res
 
 

@@ -623,3 +623,21 @@ def test_adjoint_matches_stored_finite_differences():
     assert np.max(np.abs(gt[coords] - np.asarray(fd["tau_fd"]))) <= 1e-10 * np.max(np.abs(gt))
     d_fd = np.asarray(fd["direction_fd"])
     assert np.max(np.abs(W.fd_directions(wl.n_radial) @ gt - d_fd) / np.abs(d_fd)) <= 1e-8
+
+
+# the bench's parallel-efficiency reporter against the paper's own table
+# (tests/golden/paper_table2.json: section 6.8, Table 2)
+def test_parallel_efficiency_reproduces_table_2():
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    with open(os.path.join(GOLDEN, "paper_table2.json")) as f:
+        table = json.load(f)
+    for row in table["rows"]:
+        eta = bench.parallel_efficiency(row["single_s"], row["multi_s"], table["cores"])
+        assert round(100 * eta) == row["efficiency_pct"], row
+    # the unrounded values of the three rows
+    etas = [bench.parallel_efficiency(r["single_s"], r["multi_s"], 4) for r in table["rows"]]
+    assert np.allclose(etas, [0.4310, 0.6012, 0.7015], atol=5e-4)
