@@ -348,7 +348,9 @@ wkern_status wkern_set_chunks(wkern_plan_t plan, int32_t chunks);
 wkern_status wkern_sync_status(wkern_plan_t plan, void* stream);
 
 /* Release the plan and everything it owns.  Synchronises the plan's device
- * first.  NULL is accepted and ignored. */
+ * first.  NULL is accepted and ignored.  With canaries on (WKERN_CANARY at
+ * plan creation) the guard bands are checked first: DEVICE, with the buffer
+ * named, if one changed; the plan is released all the same. */
 wkern_status wkern_destroy(wkern_plan_t plan);
 
 /* Static description of a status code. */

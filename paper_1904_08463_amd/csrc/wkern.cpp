@@ -1373,12 +1373,14 @@ wkern_status wkern_sync_status(wkern_plan_t plan, void* stream) {
 wkern_status wkern_destroy(wkern_plan_t plan) {
   clear_error();
   if (!plan) return WKERN_OK;
+  wkern_status s = WKERN_OK;
   {
     DeviceGuard guard(plan->desc.device);
     (void)hipDeviceSynchronize();
+    if (plan->canary) s = check_canaries(plan);
     delete plan;
   }
-  return WKERN_OK;
+  return s;
 }
 
 }  // extern "C"

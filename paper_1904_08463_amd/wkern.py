@@ -412,9 +412,10 @@ class Plan:
             os_, os_, int(self.support[p]), int(self.support[p])) for p in range(self.n_planes)]
 
     def close(self):
-        if getattr(self, "_h", None):
-            _check(load_library().wkern_destroy(self._h))
-            self._h = None
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None  # released even when destroy reports an error
+            _check(load_library().wkern_destroy(h))
 
     def __del__(self):
         try:
@@ -472,9 +473,10 @@ class FFT2DPlan:
         return out
 
     def close(self):
-        if getattr(self, "_h", None):
-            _check(load_library().wkern_fft2d_destroy(self._h))
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            _check(load_library().wkern_fft2d_destroy(h))
 
     def __del__(self):
         try:

@@ -348,4 +348,24 @@ def test_canaries_hold_on_every_path(env, precision, variant):
     env("WKERN_FAULT", None)
     assert ei.value.status == DEVICE and "canary overwritten after" in str(ei.value), str(ei.value)
     plan.sync_status()  # refilled
+    plan.close()  # checks the bands once more
+
+
+def test_canary_reported_at_destroy(env):
+    """With canaries on, destroying the plan checks the bands: a byte the host
+    hook changes is reported by wkern_destroy, and the plan is released all
+    the same (a second close is a no-op)."""
+    from paper_1904_08463_amd import Plan
+    from paper_1904_08463_amd.wkern import WkernError
+    wl = W.plain()
+    env("WKERN_CANARY", "1")
+    plan = Plan.from_workload(wl)
+    env("WKERN_CANARY", None)
+    taper, w = _inputs(wl)
+    plan.generate(taper, w)
+    env("WKERN_FAULT", "canary")
+    with pytest.raises(WkernError) as ei:
+        plan.close()
+    env("WKERN_FAULT", None)
+    assert ei.value.status == DEVICE and "canary" in str(ei.value)
     plan.close()
