@@ -39,6 +39,48 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
+// The six split-BF16 products of one 16-node step, interleaved over the
+// output blocks (rb, cb) so that consecutive MFMAs are independent: the five
+// small products (02, 11, 20, 01, 10) accumulate into lo, the 00 product
+// into hi (block b = rb * CBW + cb).
+template <int RBW, int CBW>
+__device__ __forceinline__ void mfma_split6(const bf16x8 (&aq)[RBW][3], const bf16x8 (&bq)[CBW][3],
+                                            f32x16 (&lo)[RBW * CBW], f32x16 (&hi)[RBW * CBW]) {
+#pragma unroll
+  for (int term = 0; term < 6; ++term) {
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb) {
+#pragma unroll
+      for (int cb = 0; cb < CBW; ++cb) {
+        const int b = rb * CBW + cb;
+        switch (term) {
+          case 0: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][2], lo[b], 0, 0, 0); break;
+          case 1: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][1], lo[b], 0, 0, 0); break;
+          case 2: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[cb][0], lo[b], 0, 0, 0); break;
+          case 3: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][1], lo[b], 0, 0, 0); break;
+          case 4: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][0], lo[b], 0, 0, 0); break;
+          default: hi[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][0], hi[b], 0, 0, 0); break;
+        }
+      }
+    }
+  }
+}
+
+// End of a sub-chunk: the FP32 sums of the 00 product (hi) and of the small
+// products (lo) go into FP64 running sums, and start again from zero.
+template <int NB>
+__device__ __forceinline__ void flush_fp64(double (&accd)[NB][16], f32x16 (&hi)[NB],
+                                           f32x16 (&lo)[NB]) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accd[b][r] += (double)hi[b][r] + (double)lo[b][r];
+      hi[b][r] = 0.f;
+      lo[b][r] = 0.f;
+    }
+}
+
 // --------------------------------------------------------------------------
 // Discrete HT matrix (section 4.3): M[k, i] = 2 pi J0(2 pi rho_k r_i) r_i dr,
 // midpoint nodes r_i = (i + 1/2) dr, rho_k = k drho.  FP64 with the device
@@ -539,14 +581,7 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_lds(
         for (int q = 0; q < 3; ++q) bq[cb][q] = bn[cb][q];
     }
     if (((kb + kKB - t.k0) % kSubChunk) == 0) {
-#pragma unroll
-      for (int b = 0; b < RB * CB; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          accd[b][r] += (double)hi[b][r] + (double)lo[b][r];
-          hi[b][r] = 0.f;
-          lo[b][r] = 0.f;
-        }
+      flush_fp64(accd, hi, lo);
     }
     if (more) {
 #pragma unroll
@@ -817,33 +852,9 @@ __global__ __launch_bounds__(256) void k_contract_bf16x6_ring(
     // products interleaved over the output blocks so consecutive MFMAs are
     // independent; row blocks past the tile's last row compute on padded
     // rows of M and are not stored
-#pragma unroll
-    for (int term = 0; term < 6; ++term) {
-#pragma unroll
-      for (int rb = 0; rb < RBW; ++rb) {
-#pragma unroll
-        for (int cb = 0; cb < CBW; ++cb) {
-          const int b = rb * CBW + cb;
-          switch (term) {
-            case 0: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][2], lo[b], 0, 0, 0); break;
-            case 1: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][1], lo[b], 0, 0, 0); break;
-            case 2: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[cb][0], lo[b], 0, 0, 0); break;
-            case 3: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][1], lo[b], 0, 0, 0); break;
-            case 4: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][0], lo[b], 0, 0, 0); break;
-            default: hi[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][0], hi[b], 0, 0, 0); break;
-          }
-        }
-      }
-    }
+    mfma_split6<RBW, CBW>(aq, bq, lo, hi);
     if (((s + 1) * 16) % kSubChunk == 0) {
-#pragma unroll
-      for (int b = 0; b < RBW * CBW; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          accd[b][r] += (double)hi[b][r] + (double)lo[b][r];
-          hi[b][r] = 0.f;
-          lo[b][r] = 0.f;
-        }
+      flush_fp64(accd, hi, lo);
     }
   };
 
@@ -1061,33 +1072,9 @@ __global__ __launch_bounds__(64 * WR * WC) void k_contract_bf16x6_ringf(
 #pragma unroll
     for (int rb = 0; rb < RBW; ++rb)
       fragment(slot, (rbBase + rb) * 32 + rr, aq[rb][0], aq[rb][1], aq[rb][2]);
-#pragma unroll
-    for (int term = 0; term < 6; ++term) {
-#pragma unroll
-      for (int rb = 0; rb < RBW; ++rb) {
-#pragma unroll
-        for (int cb = 0; cb < CBW; ++cb) {
-          const int b = rb * CBW + cb;
-          switch (term) {
-            case 0: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][2], lo[b], 0, 0, 0); break;
-            case 1: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][1], lo[b], 0, 0, 0); break;
-            case 2: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[cb][0], lo[b], 0, 0, 0); break;
-            case 3: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][1], lo[b], 0, 0, 0); break;
-            case 4: lo[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[cb][0], lo[b], 0, 0, 0); break;
-            default: hi[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[cb][0], hi[b], 0, 0, 0); break;
-          }
-        }
-      }
-    }
+    mfma_split6<RBW, CBW>(aq, bq, lo, hi);
     if (((s + 1) * 16) % kSubChunk == 0) {
-#pragma unroll
-      for (int b = 0; b < RBW * CBW; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          accd[b][r] += (double)hi[b][r] + (double)lo[b][r];
-          hi[b][r] = 0.f;
-          lo[b][r] = 0.f;
-        }
+      flush_fp64(accd, hi, lo);
     }
   };
 
@@ -1252,12 +1239,12 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringh(
     if (s + NS - 1 < nst) issue(std::integral_constant<int, KN>{}, s + NS - 1);
     const uint4* slot = slot_of(kc);
     // the 8 nodes hb*8 .. hb*8 + 7 of this lane's column, split into terms
-    bf16x8 bq[3];
+    bf16x8 bq[1][3];
     {
       const float4* bs = (const float4*)(slot + AU);
       const float4 a = bs[4 * col + ((2 * hb) ^ sw)];
       const float4 b = bs[4 * col + ((2 * hb + 1) ^ sw)];
-      split_bf16x3(a, b, bq[0], bq[1], bq[2]);
+      split_bf16x3(a, b, bq[0][0], bq[0][1], bq[0][2]);
     }
     bf16x8 aq[RB][3];
 #pragma unroll
@@ -1265,29 +1252,9 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringh(
 #pragma unroll
       for (int term = 0; term < 3; ++term)
         aq[rb][term] = as_bf16x8(slot[(hb * 3 + term) * BM + rb * 32 + rr]);
-#pragma unroll
-    for (int term = 0; term < 6; ++term) {
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        switch (term) {
-          case 0: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[2], lo[rb], 0, 0, 0); break;
-          case 1: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[1], lo[rb], 0, 0, 0); break;
-          case 2: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[0], lo[rb], 0, 0, 0); break;
-          case 3: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[1], lo[rb], 0, 0, 0); break;
-          case 4: lo[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[0], lo[rb], 0, 0, 0); break;
-          default: hi[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[0], hi[rb], 0, 0, 0); break;
-        }
-      }
-    }
+    mfma_split6<RB, 1>(aq, bq, lo, hi);
     if (((s + 1) * 16) % kSubChunk == 0) {
-#pragma unroll
-      for (int b = 0; b < RB; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          accd[b][r] += (double)hi[b][r] + (double)lo[b][r];
-          hi[b][r] = 0.f;
-          lo[b][r] = 0.f;
-        }
+      flush_fp64(accd, hi, lo);
     }
   };
 
@@ -1362,6 +1329,23 @@ __device__ __forceinline__ void two_sum_into(float& big, float& comp, float hi) 
   const float e = (big - (s - bp)) + (hi - bp);
   big = s;
   comp += e;
+}
+
+// End of a sub-chunk in the two-sum variants: the FP32 sum of the 00
+// product (hi) is added to the pair (big, comp) with an exact two-sum and
+// starts again from zero; comp also holds the small products.
+template <int NB>
+__device__ __forceinline__ void flush_two_sum(float (&big)[NB][16], f32x16 (&comp)[NB],
+                                              f32x16 (&hi)[NB]) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      float c = comp[b][r];
+      two_sum_into(big[b][r], c, hi[b][r]);
+      comp[b][r] = c;
+      hi[b][r] = 0.f;
+    }
 }
 
 __global__ __launch_bounds__(512) void k_contract_bf16x6_ringr(
@@ -1473,14 +1457,14 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringr(
   // alternate, so that stage s + 1's values are read and split while the
   // MFMAs of stage s run.  M's terms need no arithmetic and are read for the
   // current stage only.
-  bf16x8 bq0[3], bq1[3], aq[RB][3];
+  bf16x8 bq0[1][3], bq1[1][3], aq[RB][3];
   auto read_b = [&](auto kc, auto fc) __attribute__((always_inline)) {
     constexpr int F = decltype(fc)::value;
     const float4* bs = (const float4*)(slot_of(kc) + AU);
     const float4 x = bs[4 * col + ((2 * hb) ^ sw)];
     const float4 y = bs[4 * col + ((2 * hb + 1) ^ sw)];
-    if constexpr (F == 0) split_bf16x3(x, y, bq0[0], bq0[1], bq0[2]);
-    else split_bf16x3(x, y, bq1[0], bq1[1], bq1[2]);
+    if constexpr (F == 0) split_bf16x3(x, y, bq0[0][0], bq0[0][1], bq0[0][2]);
+    else split_bf16x3(x, y, bq1[0][0], bq1[0][1], bq1[0][2]);
   };
   auto read_a = [&](auto kc) __attribute__((always_inline)) {
     const uint4* slot = slot_of(kc);
@@ -1493,20 +1477,7 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringr(
   auto mfma = [&](auto fc) __attribute__((always_inline)) {
     constexpr int F = decltype(fc)::value;
     auto& bq = F == 0 ? bq0 : bq1;
-#pragma unroll
-    for (int term = 0; term < 6; ++term) {
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        switch (term) {
-          case 0: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[2], comp[rb], 0, 0, 0); break;
-          case 1: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[1], comp[rb], 0, 0, 0); break;
-          case 2: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[0], comp[rb], 0, 0, 0); break;
-          case 3: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[1], comp[rb], 0, 0, 0); break;
-          case 4: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[0], comp[rb], 0, 0, 0); break;
-          default: hi[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[0], hi[rb], 0, 0, 0); break;
-        }
-      }
-    }
+    mfma_split6<RB, 1>(aq, bq, comp, hi);
   };
   // Step s (K = s mod 24; slot and register set s mod 3, screen terms
   // s mod 2, flush every 8 steps): stage s + 1 goes from its registers to
@@ -1528,15 +1499,7 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringr(
     read_b(std::integral_constant<int, SN>{}, std::integral_constant<int, FN>{});
     mfma(std::integral_constant<int, FC>{});
     if constexpr ((K + 1) % (kSubChunk / 16) == 0) {
-#pragma unroll
-      for (int b = 0; b < RB; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          float c = comp[b][r];
-          two_sum_into(big[b][r], c, hi[b][r]);
-          comp[b][r] = c;
-          hi[b][r] = 0.f;
-        }
+      flush_two_sum(big, comp, hi);
     }
   };
   static_assert(24 % (kSubChunk / 16) == 0, "flush period divides the unrolled steps");
@@ -1689,11 +1652,11 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringw(
     __builtin_amdgcn_sched_barrier(0);
     store_a(std::integral_constant<int, SA>{}, (K + AHEAD) % NSL);
     load_a(std::integral_constant<int, SA>{}, min(s + AHEAD + 3, nst - 1));
-    bf16x8 bq[3];
-    if constexpr (SB == 0) split_bf16x3(b0x, b0y, bq[0], bq[1], bq[2]);
-    else if constexpr (SB == 1) split_bf16x3(b1x, b1y, bq[0], bq[1], bq[2]);
-    else if constexpr (SB == 2) split_bf16x3(b2x, b2y, bq[0], bq[1], bq[2]);
-    else split_bf16x3(b3x, b3y, bq[0], bq[1], bq[2]);
+    bf16x8 bq[1][3];
+    if constexpr (SB == 0) split_bf16x3(b0x, b0y, bq[0][0], bq[0][1], bq[0][2]);
+    else if constexpr (SB == 1) split_bf16x3(b1x, b1y, bq[0][0], bq[0][1], bq[0][2]);
+    else if constexpr (SB == 2) split_bf16x3(b2x, b2y, bq[0][0], bq[0][1], bq[0][2]);
+    else split_bf16x3(b3x, b3y, bq[0][0], bq[0][1], bq[0][2]);
     load_b(std::integral_constant<int, SB>{}, min(s + 4, nst - 1));
     const uint4* slot = ringA[K % NSL];
     bf16x8 aq[RB][3];
@@ -1702,30 +1665,9 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringw(
 #pragma unroll
       for (int term = 0; term < 3; ++term)
         aq[rb][term] = as_bf16x8(slot[(hb * 3 + term) * BM + rb * 32 + rr]);
-#pragma unroll
-    for (int term = 0; term < 6; ++term) {
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        switch (term) {
-          case 0: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[2], comp[rb], 0, 0, 0); break;
-          case 1: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[1], comp[rb], 0, 0, 0); break;
-          case 2: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][2], bq[0], comp[rb], 0, 0, 0); break;
-          case 3: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[1], comp[rb], 0, 0, 0); break;
-          case 4: comp[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][1], bq[0], comp[rb], 0, 0, 0); break;
-          default: hi[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[rb][0], bq[0], hi[rb], 0, 0, 0); break;
-        }
-      }
-    }
+    mfma_split6<RB, 1>(aq, bq, comp, hi);
     if constexpr ((K + 1) % (kSubChunk / 16) == 0) {
-#pragma unroll
-      for (int b = 0; b < RB; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          float c = comp[b][r];
-          two_sum_into(big[b][r], c, hi[b][r]);
-          comp[b][r] = c;
-          hi[b][r] = 0.f;
-        }
+      flush_two_sum(big, comp, hi);
     }
     if constexpr ((K + 1) % PERIOD == 0) barrier();
   };
