@@ -192,11 +192,11 @@ SPLIT_ONLY = ("ring128x128", "ring64x256", "ring32x512", "ringh64x256", "ringr64
 @pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_every_contraction_variant(variant, precision):
-    if precision == "fp32" and variant in SPLIT_ONLY:
-        pytest.skip("split-BF16 only variant")
     """Every candidate the autotuner may pick, on ragged random planes (one K-chunk
     of 32 stages, and one of 16: Nr 96 pads to 256) and on sampled planes of
     the paper workload."""
+    if precision == "fp32" and variant in SPLIT_ONLY:
+        pytest.skip("split-BF16 only variant")
     for wl, planes in ((W.random_small(5, n_planes=45, n_radial=300, os_=5, max_support=41), None),
                        (W.random_small(7, n_planes=9, n_radial=96, os_=3, max_support=21), None),
                        (W.paper(), [0, 3, 100, 255])):
