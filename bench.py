@@ -729,7 +729,8 @@ def main():
     c16 = stages.get("contraction")
     c32 = paths.get("fp32", {}).get("stage_ms", {}).get("contraction")
     speedups["vs_fp32_hankel_contraction"] = c32 / c16 if c16 and c32 else None
-    combine = ("fp32 two-sum pair" if info["variant"] in ("ringr64x256", "ringw64x256") else "fp64")
+    combine = {"ringr64x256": "fp32 two-sum pair",
+               "ringw64x256": "fp64 for the 00 product"}.get(info["variant"], "fp64")
 
     line = {
         "metric": "w-kernels/sec at <=1e-6 rel err (split-BF16 Hankel; FP32 Hankel beside it)",

@@ -103,9 +103,11 @@ typedef enum {
  * exact split of its FP32 value (ringf variants) or split at plan time from
  * its FP64 value (the others).  Both paths accumulate in FP32 over
  * sub-chunks of 128 radial nodes; the sub-chunk sums go into an FP64
- * running sum or, in ringr64x256 and ringw64x256 (the autotuner's usual
- * choice), into an FP32 pair formed with an exact two-sum (about 48 bits;
- * measured at the same error). */
+ * running sum or, in ringr64x256, into an FP32 pair formed with an exact
+ * two-sum (about 48 bits; measured at the same error).  ringw64x256 (the
+ * autotuner's usual choice) adds only the 00 product's sub-chunk sums to
+ * the FP64 running sum and keeps the five small products in FP32 over the
+ * whole K-chunk (at most 2048 nodes; emulated at the same error). */
 typedef enum { WKERN_PREC_FP32 = 0, WKERN_PREC_BF16X6 = 1 } wkern_precision;
 
 /* Interpolation of the radial line (section 4.3.2). */
@@ -317,8 +319,8 @@ wkern_status wkern_set_graph(wkern_plan_t plan, int32_t enable);
 /* Override the autotuner's choice of contraction variant (0 <= variant <
  * n_variants).  All variants compute the same products in the same order
  * per output element; they differ in tiling, in how operands reach LDS and,
- * for ringr64x256 and ringw64x256, in the running sum (an FP32 two-sum pair
- * instead of FP64), so results can differ in the last bits.  The
+ * for ringr64x256 and ringw64x256, in the running sum (an FP32 two-sum pair;
+ * FP64 for the 00 product only), so results can differ in the last bits.  The
  * autotuner's candidates are the variants that stage FP32 operands or M's
  * plan-time BF16 terms with the FP32 screen.  Indices: 0 wave32x64,
  * 1 wave32x128, 2 lds128x128, 3 lds64x256, 4 ring128x128, 5 ring64x256,

@@ -74,9 +74,10 @@ enum ContractVariant {
   // the same tile with operands staged through registers and the running
   // sum held as an FP32 two-sum pair (split-BF16 only)
   kRingR64x256 = 11,
-  // the same with the screen loaded straight into registers by the lanes
-  // that use it and M's terms through a deep LDS ring, one barrier every 4
-  // stages (split-BF16 only)
+  // the same tile with the screen loaded straight into registers by the
+  // lanes that use it, M's terms through a deep LDS ring, one barrier every
+  // 4 stages, and an FP64 running sum of the 00 product (the small products
+  // in FP32 over the K-chunk) (split-BF16 only)
   kRingW64x256 = 12,
   kNumVariants = 13
 };

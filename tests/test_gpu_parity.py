@@ -213,31 +213,38 @@ def test_every_contraction_variant(variant, precision):
         plan.close()
 
 
-def test_two_sum_variants_agree():
-    """ringr64x256 and ringw64x256 run the same arithmetic in the same order
-    (only the way operands reach the lanes differs): their caches agree bit
-    for bit.  ringh64x256 keeps the running sum in FP64 instead of the FP32
-    two-sum pair: the radial lines agree to 1e-8 of each plane's peak, far
-    inside the 1e-6 gate (the emulated difference of the two sums is below
-    1e-9)."""
+def test_running_sum_variants_agree():
+    """ringh64x256 keeps an FP64 running sum of every sub-chunk's sums,
+    ringr64x256 an FP32 two-sum pair, and ringw64x256 an FP64 running sum of
+    the 00 product with the small products left in FP32 over the K-chunk.
+    Their radial lines agree to 1e-8 of each plane's peak, far inside the 1e-6
+    gate (the emulated differences of the three sums are below 1e-9).  Their
+    caches, where a line difference can move the FP32 spline coefficients by
+    an ulp, agree within the split path's gate."""
     wl = W.paper()
     plan = _plan(wl, "bf16x6")
     taper, w = _inputs(wl)
     got = {}
     lines = {}
-    for v in ("ringr64x256", "ringw64x256", "ringh64x256"):
+    for v in ("ringh64x256", "ringr64x256", "ringw64x256"):
         plan.set_variant(v)
         got[v] = plan.generate(taper, w).cpu().numpy()
         lines[v] = plan.generate_radial(taper, w).cpu().numpy()
-    assert np.array_equal(got["ringr64x256"].view(np.uint64), got["ringw64x256"].view(np.uint64))
     loffs = np.concatenate([[0], np.cumsum(plan.nrho)])
-    worst = 0.0
-    for p in range(wl.n_planes):
-        a = lines["ringr64x256"][loffs[p]:loffs[p + 1]]
-        b = lines["ringh64x256"][loffs[p]:loffs[p + 1]]
-        worst = max(worst, float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
-    print(f"two-sum vs FP64 running sum: worst line difference {worst:.3e}", flush=True)
-    assert worst <= 1e-8
+    for v in ("ringr64x256", "ringw64x256"):
+        worst_l = worst_c = 0.0
+        for p in range(wl.n_planes):
+            a = lines[v][loffs[p]:loffs[p + 1]]
+            b = lines["ringh64x256"][loffs[p]:loffs[p + 1]]
+            worst_l = max(worst_l, float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+            o0, o1 = int(plan.offsets[p]), int(plan.offsets[p + 1])
+            a = got[v][o0:o1]
+            b = got["ringh64x256"][o0:o1]
+            worst_c = max(worst_c, float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+        print(f"{v} vs ringh64x256: worst line difference {worst_l:.3e}, cache {worst_c:.3e}",
+              flush=True)
+        assert worst_l <= 1e-8
+        assert worst_c <= GATE["bf16x6"]
     plan.close()
 
 
