@@ -111,10 +111,6 @@ inline ScreenLayout screen_layout(int precision, int variant) {
   return variant == kRingW64x256 && precision == 1 ? kScreenGroups : kScreenColumns;
 }
 
-// Resample units: blocks of at most this many consecutive elements of one
-// plane (the full cache's units, and the truncated layout's).
-constexpr int kUnitElems = 65536;
-
 // Planes of a pipeline chunk start at multiples of this (in sorted order),
 // so no contraction column block straddles two chunks.
 constexpr int kChunkAlign = 128;

@@ -34,6 +34,10 @@ __host__ __device__ inline void magic_div24(uint32_t d, uint32_t& m, int32_t& sh
   sh = L - 32;
 }
 
+// Resample units: blocks of at most this many consecutive elements of one
+// plane (the full cache's units, and the truncated layout's).
+constexpr int kUnitElems = 65536;
+
 // One block of output elements [e0, e1) of plane p (plane-local indices).
 struct ResampleUnit {
   int32_t p;
