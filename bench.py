@@ -729,8 +729,10 @@ def main():
     c16 = stages.get("contraction")
     c32 = paths.get("fp32", {}).get("stage_ms", {}).get("contraction")
     speedups["vs_fp32_hankel_contraction"] = c32 / c16 if c16 and c32 else None
-    combine = {"ringr64x256": "fp32 two-sum pair",
-               "ringw64x256": "fp64 for the 00 product"}.get(info["variant"], "fp64")
+    # the running sum that carries the 128-node FP32 sub-chunk sums
+    combine = {"ringr64x256": "fp32 two-sum running sum",
+               "ringw64x256": "fp64 running sum of the 00 product"}.get(info["variant"],
+                                                                      "fp64 running sum")
 
     line = {
         "metric": "w-kernels/sec at <=1e-6 rel err (split-BF16 Hankel; FP32 Hankel beside it)",
@@ -746,7 +748,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"bf16x6 (fp32 accumulate, {combine} combine)",
+        "dtype": f"bf16x6 (fp32 accumulate, {combine})",
         "data": "synthetic",
         "config": {"workload": "batch: 16 ch x 1024 w-planes, Nr 8192, os 8, S 7..255, "
                                "2048^2 @ 3.5 arcsec, PSWF taper; 16384 kernels per step, "
