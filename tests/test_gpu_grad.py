@@ -10,7 +10,9 @@ Gates (error = max |g - g_ref| / max |g_ref| unless stated):
 - end to end (device forward, torch loss, device backward): dL/dtaper 1e-4;
   dL/dw W_GATE (2e-3 split-BF16, 1e-2 FP32), since the window loss sees only
   the kernel tail (about 5e-6 of the peak) and dL/dw inherits the forward's
-  absolute error there; a directional derivative within 1e-3 of |FD|.
+  absolute error there; a directional derivative within 1e-3 of |FD|;
+- end to end with the kernel's radius-weighted energy as the loss (it sees
+  the whole kernel): dL/dtaper and dL/dw 1e-4.
 """
 import json
 import os
@@ -126,6 +128,53 @@ def test_autograd_end_to_end(grad_ref):
     dd = float(np.dot(gt, v))
     print(f"directional FD {fd:.6e}, device {dd:.6e}, oracle {float(np.dot(gt_ref, v)):.6e}", flush=True)
     assert abs(dd - fd) <= 1e-3 * abs(fd)
+
+
+def test_autograd_end_to_end_kernel_moment():
+    """The same end-to-end path with a loss that sees the whole kernel: its
+    energy weighted by the squared radius, L = sum_p sum (X^2 + Y^2) / (os h)^2
+    |K_p|^2 (dL/dK = 2 weight K), which grows as the kernel widens with |w|.
+    dL/dw and dL/dtaper of the device forward + torch loss + device backward
+    both meet the 1e-4 gate against the oracle's adjoint of the oracle's
+    cache, in both precisions.  (The window loss above sees only the tail,
+    where the forward's absolute error is a large fraction of the values; the
+    plain kernel energy is nearly independent of w, so its dL/dw is a small
+    difference of large terms.)"""
+    from paper_1904_08463_amd import Plan
+    from paper_1904_08463_amd.autograd import wkernels
+    wl = W.grad()
+    assert np.all(wl.support == wl.support[0])
+    S, os_ = int(wl.support[0]), wl.oversampling
+    h = (S - 1) // 2
+    x = os_ * (np.arange(S)[None, None, None, :] - h) - np.arange(os_)[None, :, None, None]
+    y = os_ * (np.arange(S)[None, None, :, None] - h) - np.arange(os_)[:, None, None, None]
+    weight = ((x ** 2 + y ** 2) / float(os_ * h) ** 2).astype(np.float64)
+    tau = wl.taper.astype(np.float64)
+    print("case grad workload radius-weighted energy: oracle forward + adjoint (CPU)", flush=True)
+    caches, _ = H.generate(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, tau, wl.w,
+                           wl.support, wl.radial_refine, wl.interp)
+    loss_ref = float(sum(np.sum(weight * np.abs(c) ** 2) for c in caches))
+    gt_ref, gw_ref = A.grad(wl.image_size, wl.cellsize, wl.n_radial, wl.oversampling, tau, wl.w,
+                            wl.support, [2.0 * weight * c for c in caches], wl.radial_refine,
+                            wl.interp)
+    del caches
+    wt = torch.from_numpy(weight.reshape(1, -1).astype(np.float32)).cuda()
+    for precision in ("bf16x6", "fp32"):
+        print(f"case grad workload radius-weighted energy precision={precision}", flush=True)
+        plan = Plan.from_workload(wl, precision=precision)
+        taper = torch.from_numpy(wl.taper).cuda().requires_grad_(True)
+        w = torch.from_numpy(wl.w).cuda().requires_grad_(True)
+        k = wkernels(taper, w, plan).view(wl.n_planes, -1)
+        loss = (wt * k.abs() ** 2).sum(dtype=torch.float64)
+        loss.backward()
+        plan.close()
+        gt = taper.grad.cpu().numpy().astype(np.float64)
+        gw = w.grad.cpu().numpy()
+        e_t, e_w = _rel(gt, gt_ref), _rel(gw, gw_ref)
+        print(f"{precision}: loss {float(loss):.9e} (oracle {loss_ref:.9e}); "
+              f"dL/dtaper err {e_t:.2e}, dL/dw err {e_w:.2e}", flush=True)
+        assert abs(float(loss) - loss_ref) / loss_ref < 1e-5
+        assert e_t <= GATE and e_w <= GATE
 
 
 FD_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grad_fd.json")
