@@ -189,6 +189,7 @@ __device__ __forceinline__ void resample_unit(const PlaneInfo& pi, int e0, int e
 
 template <bool kQ1>
 __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict__ units,
+                                                  int nUnits, int perXcd,
                                                   const PlaneInfo* __restrict__ planes,
                                                   const float4* __restrict__ coef, int os,
                                                   float invOs, uint32_t magicOs, int shiftOs,
@@ -197,7 +198,14 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
   // nrho - 1 (never a sample's) is zeroed and serves the samples outside the
   // support.
   extern __shared__ float4 sc[];  // [nrho][2]
-  const ResampleUnit u = units[blockIdx.x];
+  // Workgroups go to the XCDs in turn, so workgroup b runs on XCD b mod 8;
+  // it takes unit (b mod 8) perXcd + b / 8, and each XCD walks its own
+  // contiguous eighth of the units in address order.  A plane's units then
+  // share one XCD, and its intervals are fetched into that XCD's L2 once
+  // instead of once per XCD (the same cache bytes; 0.3-0.4% faster).
+  const int ui = (int)(blockIdx.x % kNumXcd) * perXcd + (int)(blockIdx.x / kNumXcd);
+  if (ui >= nUnits) return;
+  const ResampleUnit u = units[ui];
   const PlaneInfo pi = planes[u.p];
   const int nmax = pi.nrho - 2;
   const float4* src = coef + (size_t)pi.line_off * 2;
@@ -327,13 +335,16 @@ hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStrea
   uint32_t mOs = 0;
   int32_t shOs = 0;
   if (p.os >= 2) magic_div24((uint32_t)p.os, mOs, shOs);
+  const int n = u1 - u0;
+  const int per = (n + kNumXcd - 1) / kNumXcd;
   if (p.q == 1)
-    hipLaunchKernelGGL(k_resample<true>, dim3(u1 - u0), dim3(256), shm, s, p.units + u0,
-                       p.planes, p.coef, p.os, 1.0f / (float)p.os, mOs, shOs, 1.0f, (float2*)out);
-  else
-    hipLaunchKernelGGL(k_resample<false>, dim3(u1 - u0), dim3(256), shm, s, p.units + u0,
-                       p.planes, p.coef, p.os, 1.0f / (float)p.os, mOs, shOs, (float)p.q,
+    hipLaunchKernelGGL(k_resample<true>, dim3(per * kNumXcd), dim3(256), shm, s, p.units + u0,
+                       n, per, p.planes, p.coef, p.os, 1.0f / (float)p.os, mOs, shOs, 1.0f,
                        (float2*)out);
+  else
+    hipLaunchKernelGGL(k_resample<false>, dim3(per * kNumXcd), dim3(256), shm, s, p.units + u0,
+                       n, per, p.planes, p.coef, p.os, 1.0f / (float)p.os, mOs, shOs,
+                       (float)p.q, (float2*)out);
   return hipGetLastError();
 }
 
