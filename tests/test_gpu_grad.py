@@ -168,12 +168,13 @@ def test_autograd_end_to_end_kernel_moment():
         loss = (wt * k.abs() ** 2).sum(dtype=torch.float64)
         loss.backward()
         plan.close()
+        loss = float(loss.detach())
         gt = taper.grad.cpu().numpy().astype(np.float64)
         gw = w.grad.cpu().numpy()
         e_t, e_w = _rel(gt, gt_ref), _rel(gw, gw_ref)
-        print(f"{precision}: loss {float(loss):.9e} (oracle {loss_ref:.9e}); "
+        print(f"{precision}: loss {loss:.9e} (oracle {loss_ref:.9e}); "
               f"dL/dtaper err {e_t:.2e}, dL/dw err {e_w:.2e}", flush=True)
-        assert abs(float(loss) - loss_ref) / loss_ref < 1e-5
+        assert abs(loss - loss_ref) / loss_ref < 1e-5
         assert e_t <= GATE and e_w <= GATE
 
 
