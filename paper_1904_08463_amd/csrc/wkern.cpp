@@ -484,9 +484,9 @@ static wkern_status build_chunks(wkern_plan_s* pl, int want) {
   pl->chunkJ = make_chunks(bytesSorted, want);
   pl->nChunks = (int)pl->chunkJ.size() - 1;
 
-  // resample units: blocks of at most 65536 elements of one plane (multiples
-  // of 1024, so every wave chunk starts at a multiple of its size), in chunk
-  // order
+  // resample units: blocks of at most kUnitElems elements of one plane (a
+  // multiple of 1024, so every wave chunk starts at a multiple of its size),
+  // in chunk order
   const int64_t unitElems = kUnitElems;
   std::vector<ResampleUnit> units;
   pl->chunkU.assign(1, 0);

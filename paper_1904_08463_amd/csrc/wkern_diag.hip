@@ -16,11 +16,15 @@ __global__ __launch_bounds__(256) void k_store_oneshot(f32x4* __restrict__ out, 
 }
 
 // The resample's structure: a block of 256 lanes walks a unit of
-// kUnitElems complex64 (512 KB) in steps of 4 KB, one 16-byte store per lane
-// per step.
-__global__ __launch_bounds__(256) void k_store_units(f32x4* __restrict__ out, int64_t n16) {
+// kUnitElems complex64 (256 KB) in steps of 4 KB, one 16-byte store per lane
+// per step, and each XCD walks its own contiguous eighth of the units
+// (block b, on XCD b mod 8, takes unit (b mod 8) perXcd + b / 8).
+__global__ __launch_bounds__(256) void k_store_units(f32x4* __restrict__ out, int64_t n16,
+                                                     int64_t nUnits, int64_t perXcd) {
   constexpr int64_t kUnit16 = (int64_t)wkern::kUnitElems / 2;  // 16-byte items per unit
-  const int64_t base = (int64_t)blockIdx.x * kUnit16;
+  const int64_t unit = (int64_t)(blockIdx.x % wkern::kNumXcd) * perXcd + blockIdx.x / wkern::kNumXcd;
+  if (unit >= nUnits) return;
+  const int64_t base = unit * kUnit16;
   const int64_t end = base + kUnit16 < n16 ? base + kUnit16 : n16;
   for (int64_t i = base + threadIdx.x; i < end; i += 256) out[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 }
@@ -49,8 +53,14 @@ extern "C" wkern_status wkern_store_ceiling(void* buf, int64_t bytes, int32_t pa
     hipLaunchKernelGGL(k_store_oneshot, dim3((uint32_t)blocks), dim3(256), 0, s, (f32x4*)buf, n16);
   } else {
     const int64_t unit16 = (int64_t)wkern::kUnitElems / 2;
-    hipLaunchKernelGGL(k_store_units, dim3((uint32_t)((n16 + unit16 - 1) / unit16)), dim3(256), 0,
-                       s, (f32x4*)buf, n16);
+    const int64_t nUnits = (n16 + unit16 - 1) / unit16;
+    const int64_t per = (nUnits + wkern::kNumXcd - 1) / wkern::kNumXcd;
+    if (per * wkern::kNumXcd > 0x7FFFFFFF) {
+      wkern::set_last_error("buffer too large for one launch");
+      return WKERN_ERR_INVALID_ARG;
+    }
+    hipLaunchKernelGGL(k_store_units, dim3((uint32_t)(per * wkern::kNumXcd)), dim3(256), 0, s,
+                       (f32x4*)buf, n16, nUnits, per);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {

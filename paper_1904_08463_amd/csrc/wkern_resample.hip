@@ -12,8 +12,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // --------------------------------------------------------------------------
 // Oversampled kernel cache (section 4.4, Algorithm 2), element
 // e = ((fv os + fu) S + b) S + a of a plane.  Full cache: a workgroup of 256
-// threads per resample unit (at most 65536 consecutive elements of one
-// plane, starting at a multiple of 512), the plane's spline intervals staged
+// threads per resample unit (at most kUnitElems consecutive elements of one
+// plane, starting at a multiple of 1024), the plane's spline intervals staged
 // in LDS once; the truncated layout writes its units the same way.  Each wave takes 128
 // consecutive elements per step (waves interleaved, 512 per step) and each
 // lane two neighbours, written with one 16-byte store: on this chip that
@@ -202,7 +202,10 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
   // it takes unit (b mod 8) perXcd + b / 8, and each XCD walks its own
   // contiguous eighth of the units in address order.  A plane's units then
   // share one XCD, and its intervals are fetched into that XCD's L2 once
-  // instead of once per XCD (the same cache bytes; 0.3-0.4% faster).
+  // instead of once per XCD (the same cache bytes).  With the intervals
+  // local, shorter units pay: see kUnitElems.  (The truncated layout's
+  // small units measured faster in plain address order, 1.13 against 1.18
+  // ms per truncated call.)
   const int ui = (int)(blockIdx.x % kNumXcd) * perXcd + (int)(blockIdx.x / kNumXcd);
   if (ui >= nUnits) return;
   const ResampleUnit u = units[ui];
