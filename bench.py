@@ -532,7 +532,7 @@ def _cpu_baselines(wl, small):
 def _store_ceilings(out, reps=5):
     """HBM store rate of the two plain-store structures over the whole
     kernel-cache buffer (wkern_store_ceiling): one 16-byte store per lane and
-    the resample's 256 KB unit walk (each XCD on its own eighth of the units).  GB/s from the best of `reps` event-timed
+    the resample's 256 KB unit walk (units dealt to the XCDs in runs of 64).  GB/s from the best of `reps` event-timed
     launches on the launching stream."""
     import torch
     from paper_1904_08463_amd import store_ceiling

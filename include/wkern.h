@@ -445,8 +445,8 @@ wkern_status wkern_wpartition(const double* w, int64_t n_records, int32_t n_plan
  * writer can take.  pattern 0: one 16-byte store per lane, after which the
  * wave ends (blocks of 256 lanes in address order; the fastest plain-store
  * structure measured on this device); pattern 1: the resample's structure, a
- * block of 256 lanes walking a 256 KB unit in 4 KB steps, each XCD walking
- * its own contiguous eighth of the units.  Asynchronous on
+ * block of 256 lanes walking a 256 KB unit in 4 KB steps, the units dealt
+ * to the XCDs in runs of 64.  Asynchronous on
  * `stream`.  Errors: INVALID_ARG, DEVICE. */
 wkern_status wkern_store_ceiling(void* buf, int64_t bytes, int32_t pattern, void* stream);
 

@@ -17,12 +17,15 @@ __global__ __launch_bounds__(256) void k_store_oneshot(f32x4* __restrict__ out, 
 
 // The resample's structure: a block of 256 lanes walks a unit of
 // kUnitElems complex64 (256 KB) in steps of 4 KB, one 16-byte store per lane
-// per step, and each XCD walks its own contiguous eighth of the units
-// (block b, on XCD b mod 8, takes unit (b mod 8) perXcd + b / 8).
+// per step, and the units go to the XCDs in runs of kXcdRun (block b, the
+// slot-th on XCD b mod 8, takes unit ((slot / run) 8 + b mod 8) run +
+// slot mod run), as in k_resample.
 __global__ __launch_bounds__(256) void k_store_units(f32x4* __restrict__ out, int64_t n16,
-                                                     int64_t nUnits, int64_t perXcd) {
+                                                     int64_t nUnits) {
   constexpr int64_t kUnit16 = (int64_t)wkern::kUnitElems / 2;  // 16-byte items per unit
-  const int64_t unit = (int64_t)(blockIdx.x % wkern::kNumXcd) * perXcd + blockIdx.x / wkern::kNumXcd;
+  constexpr int64_t run = wkern::kXcdRun;
+  const int64_t slot = blockIdx.x / wkern::kNumXcd, xcd = blockIdx.x % wkern::kNumXcd;
+  const int64_t unit = ((slot / run) * wkern::kNumXcd + xcd) * run + slot % run;
   if (unit >= nUnits) return;
   const int64_t base = unit * kUnit16;
   const int64_t end = base + kUnit16 < n16 ? base + kUnit16 : n16;
@@ -54,13 +57,14 @@ extern "C" wkern_status wkern_store_ceiling(void* buf, int64_t bytes, int32_t pa
   } else {
     const int64_t unit16 = (int64_t)wkern::kUnitElems / 2;
     const int64_t nUnits = (n16 + unit16 - 1) / unit16;
-    const int64_t per = (nUnits + wkern::kNumXcd - 1) / wkern::kNumXcd;
+    const int64_t runs = wkern::kNumXcd * (int64_t)wkern::kXcdRun;
+    const int64_t per = (nUnits + runs - 1) / runs * wkern::kXcdRun;  // blocks per XCD
     if (per * wkern::kNumXcd > 0x7FFFFFFF) {
       wkern::set_last_error("buffer too large for one launch");
       return WKERN_ERR_INVALID_ARG;
     }
     hipLaunchKernelGGL(k_store_units, dim3((uint32_t)(per * wkern::kNumXcd)), dim3(256), 0, s,
-                       (f32x4*)buf, n16, nUnits, per);
+                       (f32x4*)buf, n16, nUnits);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {

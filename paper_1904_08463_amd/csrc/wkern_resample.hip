@@ -189,7 +189,7 @@ __device__ __forceinline__ void resample_unit(const PlaneInfo& pi, int e0, int e
 
 template <bool kQ1>
 __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict__ units,
-                                                  int nUnits, int perXcd,
+                                                  int nUnits,
                                                   const PlaneInfo* __restrict__ planes,
                                                   const float4* __restrict__ coef, int os,
                                                   float invOs, uint32_t magicOs, int shiftOs,
@@ -198,15 +198,20 @@ __global__ __launch_bounds__(256) void k_resample(const ResampleUnit* __restrict
   // nrho - 1 (never a sample's) is zeroed and serves the samples outside the
   // support.
   extern __shared__ float4 sc[];  // [nrho][2]
-  // Workgroups go to the XCDs in turn, so workgroup b runs on XCD b mod 8;
-  // it takes unit (b mod 8) perXcd + b / 8, and each XCD walks its own
-  // contiguous eighth of the units in address order.  A plane's units then
-  // share one XCD, and its intervals are fetched into that XCD's L2 once
-  // instead of once per XCD (the same cache bytes).  With the intervals
-  // local, shorter units pay: see kUnitElems.  (The truncated layout's
-  // small units measured faster in plain address order, 1.13 against 1.18
-  // ms per truncated call.)
-  const int ui = (int)(blockIdx.x % kNumXcd) * perXcd + (int)(blockIdx.x / kNumXcd);
+  // Workgroups go to the XCDs in turn, so workgroup b runs on XCD b mod 8
+  // as its slot-th workgroup there (slot = b / 8).  The units are cut into
+  // runs of kXcdRun consecutive units, dealt to the XCDs in turn: XCD x
+  // takes runs x, x + 8, ..., and walks each in address order.  A plane's
+  // units then mostly share one XCD, and its intervals are fetched into
+  // that XCD's L2 once instead of once per XCD (the same cache bytes).  With
+  // the intervals local, shorter units pay: see kUnitElems.  Runs of 64
+  // units (16 MB) measured best: on two boxes 5.396-5.403 and 5.540-5.552
+  // ms against 5.424-5.428 and 5.591-5.604 with one contiguous eighth per
+  // XCD; runs of 16, 32, 128 or 512 units were slower than either.  (The
+  // truncated layout's small units measured faster in plain address order,
+  // 1.13 against 1.18 ms per truncated call.)
+  const int slot = (int)(blockIdx.x / kNumXcd), xcd = (int)(blockIdx.x % kNumXcd);
+  const int ui = ((slot / kXcdRun) * kNumXcd + xcd) * kXcdRun + slot % kXcdRun;
   if (ui >= nUnits) return;
   const ResampleUnit u = units[ui];
   const PlaneInfo pi = planes[u.p];
@@ -339,14 +344,15 @@ hipError_t launch_resample(const DevPlan& p, int u0, int u1, void* out, hipStrea
   int32_t shOs = 0;
   if (p.os >= 2) magic_div24((uint32_t)p.os, mOs, shOs);
   const int n = u1 - u0;
-  const int per = (n + kNumXcd - 1) / kNumXcd;
+  // workgroups per XCD: whole runs of kXcdRun units
+  const int per = (n + kNumXcd * kXcdRun - 1) / (kNumXcd * kXcdRun) * kXcdRun;
   if (p.q == 1)
     hipLaunchKernelGGL(k_resample<true>, dim3(per * kNumXcd), dim3(256), shm, s, p.units + u0,
-                       n, per, p.planes, p.coef, p.os, 1.0f / (float)p.os, mOs, shOs, 1.0f,
+                       n, p.planes, p.coef, p.os, 1.0f / (float)p.os, mOs, shOs, 1.0f,
                        (float2*)out);
   else
     hipLaunchKernelGGL(k_resample<false>, dim3(per * kNumXcd), dim3(256), shm, s, p.units + u0,
-                       n, per, p.planes, p.coef, p.os, 1.0f / (float)p.os, mOs, shOs,
+                       n, p.planes, p.coef, p.os, 1.0f / (float)p.os, mOs, shOs,
                        (float)p.q, (float2*)out);
   return hipGetLastError();
 }

@@ -43,6 +43,9 @@ __host__ __device__ inline void magic_div24(uint32_t d, uint32_t& m, int32_t& sh
 // 48 K, 5.63 for 16 K and 5.66 for 64 K (one box, bit-identical caches).
 constexpr int kUnitElems = 32768;
 
+// Runs of consecutive resample units dealt to the XCDs in turn (k_resample).
+constexpr int kXcdRun = 64;
+
 // One block of output elements [e0, e1) of plane p (plane-local indices).
 struct ResampleUnit {
   int32_t p;
