@@ -51,7 +51,8 @@
  * Environment (read by the host code at each call):
  * - WKERN_TUNE_CACHE=<file>: the plan-time autotuner's results persist in
  *   this text file, one line per device architecture, HIP runtime version,
- *   library ABI version and geometry bucket; a plan whose key is present
+ *   library ABI version and kernel revision, and geometry bucket; a plan
+ *   whose key is present
  *   takes the stored choice instead of timing the candidates.  Unset: every
  *   plan times them.
  * - WKERN_LOG=<level>: 0 silent (default), 1 a summary line per plan on

@@ -531,10 +531,11 @@ static wkern_status build_chunks(wkern_plan_s* pl, int want) {
 // Persistent autotuner results.  WKERN_TUNE_CACHE names a text file with
 // one line per tuned geometry, "<key> <variant> <ms of each variant>"; the
 // key holds the device architecture, the HIP runtime version, the ABI
-// version and variant count of this library, the precision and a bucket of
-// the plan's geometry (padded Nr, K-chunk, computed planes and summed line
-// lengths rounded up to powers of two, padded rows of M), so a new ROCm or
-// library version never reuses an entry.  Unset: nothing is read or written.
+// version, variant count and kernel revision of this library, the precision
+// and a bucket of the plan's geometry (padded Nr, K-chunk, computed planes
+// and summed line lengths rounded up to powers of two, padded rows of M), so
+// a new ROCm, library or kernel revision never reuses an entry.  Unset:
+// nothing is read or written.
 static std::string tune_key(const wkern_plan_s* pl, int device) {
   const char* path = std::getenv("WKERN_TUNE_CACHE");
   if (!path || !*path) return std::string();
@@ -554,9 +555,9 @@ static std::string tune_key(const wkern_plan_s* pl, int device) {
   for (char& c : arch)
     if (c == ' ') c = '_';
   char buf[384];
-  snprintf(buf, sizeof(buf), "%s|hip%d|abi%d|nv%d|prec%d|nr%d|kc%d|pc%lld|rows%d|rho%lld",
-           arch.c_str(), rt, WKERN_ABI_VERSION, (int)kNumVariants, g.precision, g.NrPad,
-           g.kchunk, pow2(g.P), g.rowsPad, pow2(sumRho));
+  snprintf(buf, sizeof(buf), "%s|hip%d|abi%d|nv%d|rev%d|prec%d|nr%d|kc%d|pc%lld|rows%d|rho%lld",
+           arch.c_str(), rt, WKERN_ABI_VERSION, (int)kNumVariants, kKernelRevision, g.precision,
+           g.NrPad, g.kchunk, pow2(g.P), g.rowsPad, pow2(sumRho));
   return std::string(buf);
 }
 

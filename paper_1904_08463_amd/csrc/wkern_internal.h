@@ -33,6 +33,11 @@ constexpr int kMaxRho = 2048;
 // Accelerator complex dies (XCDs) of an MI355X; consecutive workgroups are
 // dispatched round-robin over them.
 constexpr int kNumXcd = 8;
+// Revision of the contraction kernels' code, part of the autotuner cache key:
+// raised whenever a variant's code changes its speed, so that a stored choice
+// made with older kernels is timed again.
+constexpr int kKernelRevision = 4;
+
 // Warm-up length of the truncated spline recurrences; the neglected start
 // value is damped by (2 - sqrt 3)^16 ~ 7e-10, far below the FP32 rounding of
 // the stored coefficients (6e-8).  The recurrences' serial latency is most

@@ -205,6 +205,7 @@ def test_tuning_cache_round_trip(env, tmp_path):
     a.close()
     lines = path.read_text().splitlines()
     assert len(lines) == 1 and "|prec1|" in lines[0] and "|abi3|" in lines[0]
+    assert "|rev" in lines[0]
     # a second plan of the same geometry takes the stored result unchanged
     b = Plan.from_workload(wl, precision="bf16x6")
     assert b.info() == ia
@@ -227,6 +228,16 @@ def test_tuning_cache_round_trip(env, tmp_path):
     d = Plan.from_workload(wl, precision="fp32")
     d.close()
     assert len(path.read_text().splitlines()) == 2
+    # an entry made with another kernel revision is not reused: the plan
+    # times its candidates again and appends its own entry
+    rev = key.split("|rev")[1].split("|")[0]
+    stale = key.replace(f"|rev{rev}|", f"|rev{int(rev) - 1}|")
+    path.write_text(f"{stale} {Plan.VARIANTS.index(other)} {rest}\n")
+    e = Plan.from_workload(wl, precision="bf16x6")
+    assert e.info()["variant"] != other
+    e.close()
+    kept = path.read_text().splitlines()
+    assert len(kept) == 2 and kept[0].startswith(stale + " ") and kept[1].startswith(key + " ")
 
 
 # ---------------------------------------------------------------------------
