@@ -1556,8 +1556,9 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringr(
 // products stay in one FP32 accumulator for the whole K-chunk, where their
 // rounding (2^-24 of a sum already 2^-8 down) is far below the sub-chunk
 // sums' (emulated on the CPU: the same error as the FP64 and two-sum
-// combines, 2.2e-8; about 6% faster than the two-sum here).  The screen, written node-group-
-// major for this kernel (k_screen_f32_groups), goes straight from global
+// combines, 2.2e-8; about 6% faster than the two-sum here).  The screen,
+// written node-group-major for this kernel (k_screen_f32_groups), goes
+// straight from global
 // memory into the registers of the lane that uses it (a lane owns one column
 // and 8 nodes of each 16-node stage), four stages ahead, so it needs neither
 // LDS nor a barrier.  In the node-group-major layout a wave's load covers 32
@@ -1566,8 +1567,10 @@ __global__ __launch_bounds__(512) void k_contract_bf16x6_ringr(
 // M's terms, which all 8 waves share, go through LDS: every thread loads one
 // 16-byte item of a stage into registers three stages before it writes it
 // to a ring of 8 slots, 4 stages before the stage is used, and the
-// workgroup meets at a barrier once every 4 stages.  Between barriers the waves drift apart, so
-// one wave's split and loads overlap another's MFMAs on the same SIMD.
+// workgroup meets at a barrier once every 4 stages.  Between barriers the
+// waves drift apart, so one wave's split and loads can partly overlap
+// another's MFMAs on the same SIMD (measured: matrix and VALU work of two
+// waves on one SIMD overlap only in part, and within one wave not at all).
 // Stage t is written at step t - 4 and read at step t: a barrier ends one of
 // the steps t - 4 .. t - 1, after the write (RAW); its slot was last read at
 // step t - 8, and a barrier ends one of the steps t - 8 .. t - 5 (WAR).  No
